@@ -1,0 +1,33 @@
+"""FP64 CPU oracle for the finite-strain tangent apply v = K(u) w.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+package: only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library (no tables, no
+kernels, no helpers) and it never reads a value produced by the HIP path.
+
+What it computes is the plain definition of the discrete tangent of the paper
+(Sec. 2.1, eqs. for the weak form F, its Gateaux derivative K and the tangent
+stiffness tensor L; Sec. 2.4 for the cell-wise quadrature), for the
+compressible neo-Hookean energy of Sec. 3.2, written without sum
+factorization, without caches and without the directional-derivative trick:
+the 81-entry tangent tensor L is formed explicitly at every quadrature point
+and contracted with full (p+1)^3-term basis gradients, both
+
+* assembled into a sparse matrix (the "classical" sparse baseline, Sec. 3.2.2),
+  then multiplied with w, and
+* as a naive element loop that never forms a global matrix.
+
+Modules
+-------
+basis     1D Gauss rule, Gauss-Lobatto-Legendre support points, Lagrange basis
+mesh      structured Q_p box: numbering, trilinear geometry, basis gradients
+material  energy, first Piola-Kirchhoff stress, explicit tangent tensor
+fem       state, residual, energy, assembled tangent, naive apply
+linelast  textbook small-strain stiffness B^T D B (pin for the u = 0 limit)
+
+Every function is float64 unless it is fed complex128 input for the
+complex-step pins, in which case it works in complex128 throughout.
+"""
+
+from . import basis, mesh, material, fem, linelast  # noqa: F401
+from .mesh import BoxMesh  # noqa: F401
