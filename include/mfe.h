@@ -1,0 +1,171 @@
+/*
+ * mfe.h -- C ABI of the matrix-free finite-strain tangent library (libmfe.so).
+ *
+ * The library applies the tangent operator of a compressible neo-Hookean
+ * hyperelastic body discretised with hexahedral Q_p elements,
+ *
+ *     v_i = K(u; w, phi_i) = sum_cells sum_q JxW_q  Grad phi_i : L(F_q) : Grad w
+ *
+ * (Wichrowski et al., "Matrix-free methods for finite-strain elasticity",
+ * Sec. 2.1 eqs. DF and L for the tangent, Sec. 2.4 Alg. 1 for the cell-wise
+ * matrix-free evaluation, Sec. 2.5 Alg. 2 for the cached variant, Sec. 3.2
+ * eq. hypref for the energy), without ever forming a matrix.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh     a structured nx*ny*nz box of hexahedra whose corner vertices are
+ *          given by the caller (any positions giving positive Jacobians); the
+ *          geometry map of each cell is trilinear through its 8 vertices.
+ * Nodes    a degree-p mesh has (p*nx+1)*(p*ny+1)*(p*nz+1) nodes numbered
+ *          I + Nx*(J + Ny*K), x fastest; the Lagrange support points are
+ *          Gauss-Lobatto-Legendre points; quadrature is the (p+1)^3 Gauss rule.
+ * DoFs     node n carries dofs 3n, 3n+1, 3n+2 (x, y, z displacement).
+ * Vectors  u, w, v, r are contiguous float64 arrays of n_dofs entries in
+ *          device memory of the context's GPU, owned by the caller; they
+ *          must stay valid until the work queued on the given stream ends.
+ *          The library never frees or retains them (set_state copies u).
+ * Streams  every `stream` argument is a hipStream_t passed as void*; NULL
+ *          means the null stream.  Work is queued on that stream and only
+ *          mfe_set_state waits for it (once, to read the det F check).
+ * Errors   every call returns an mfe_status; nothing throws across the ABI.
+ *          mfe_last_error() returns a message for the last failed call on
+ *          that context (valid until the next call on it).
+ * Threads  a context is not thread-safe; use one context per host thread.
+ */
+#ifndef MFE_H
+#define MFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfe_ctx mfe_ctx;
+
+typedef enum mfe_status {
+    MFE_OK = 0,
+    MFE_EINVAL = -1,        /* bad argument: sizes, degree, aliasing, null pointer */
+    MFE_EHIP = -2,          /* a HIP runtime call failed */
+    MFE_ENOMEM = -3,        /* device allocation failed */
+    MFE_EJACOBIAN = -4,     /* det F <= 0 or det J_g <= 0 at some quadrature point */
+    MFE_ESTATE = -5,        /* apply before set_state, or cache older than the state */
+    MFE_ENOTCONV = -6,      /* reserved for the iterative solvers */
+    MFE_EUNSUPPORTED = -7   /* valid request that this build does not implement */
+} mfe_status;
+
+/* Point-wise strategies of the quadrature loop (Sec. 2.5).
+ *   MFE_OTF       on the fly, reference configuration: G = L : Grad w in
+ *                 closed form (Sec. 2.5.1), F recomputed from u and the cell
+ *                 geometry recomputed from its 8 vertices at every apply.
+ *   MFE_OTF_GEOM  as MFE_OTF but with the inverse geometry Jacobian and
+ *                 JxW stored per quadrature point (10 doubles), the layout of
+ *                 the paper's matrix-free data structures (Sec. 2.4).
+ *   MFE_T2        cached second-order data of the current configuration:
+ *                 M = J_g^-1 F^-1 (9), tau*JxW (6) and two scalars (17 doubles).
+ *   MFE_T4        cached fourth-order spatial tangent J c * JxW (21, Voigt),
+ *                 tau*JxW (6) and M (9): 36 doubles (Alg. 2; storage count of
+ *                 Sec. 3.2.3).
+ *   MFE_OTF_AD    on the fly like MFE_OTF, but G is obtained as the
+ *                 directional derivative of P along the seed dF = Grad w by
+ *                 forward-mode dual numbers (Sec. 2.5.1, eq. LG).            */
+typedef enum mfe_strategy {
+    MFE_OTF = 0,
+    MFE_OTF_GEOM = 1,
+    MFE_T2 = 2,
+    MFE_T4 = 3,
+    MFE_OTF_AD = 4
+} mfe_strategy;
+
+/* Arithmetic of the sum-factorization sweeps.  Only MFE_FP64 is implemented;
+ * the others return MFE_EUNSUPPORTED. */
+typedef enum mfe_precision {
+    MFE_FP64 = 0,
+    MFE_SF_FP32 = 1,
+    MFE_SF_BF16 = 2,
+    MFE_SF_BF16X3 = 3
+} mfe_precision;
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the
+ * context (NULL on failure).  Returns MFE_EINVAL for a bad device index. */
+int mfe_create(mfe_ctx** out, int hip_device);
+
+/* Free every device buffer of the context and the context itself.  Waits for
+ * the device to finish the context's work first.  NULL is ignored. */
+void mfe_destroy(mfe_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none; a static message if
+ * ctx is NULL).  The pointer stays valid until the next call on ctx. */
+const char* mfe_last_error(const mfe_ctx* ctx);
+
+/* Define the mesh: an nx*ny*nz box of degree-`degree` hexahedra
+ * (1 <= degree <= 6, each n >= 1).  vertex_xyz_host: host array of
+ * (nx+1)*(ny+1)*(nz+1)*3 doubles, vertex (ix,iy,iz) at index
+ * ix + (nx+1)*(iy + (ny+1)*iz), coordinates interleaved (x,y,z); copied.
+ * Checks det J_g > 0 at every quadrature point (MFE_EJACOBIAN otherwise).
+ * Resets material (mu = 1, lambda = 1), constraints, state and caches.
+ * Synchronous. */
+int mfe_mesh_box(mfe_ctx* ctx, int nx, int ny, int nz, int degree,
+                 const double* vertex_xyz_host);
+
+/* Number of dofs of the current mesh, 3 * n_nodes (0 without a mesh). */
+int64_t mfe_n_dofs(const mfe_ctx* ctx);
+
+/* Number of cells and of quadrature points of the current mesh. */
+int64_t mfe_n_cells(const mfe_ctx* ctx);
+int64_t mfe_n_qpoints(const mfe_ctx* ctx);
+
+/* Material of eq. hypref, Psi = mu/2 (tr C - 3 - 2 log J) + lambda log^2 J.
+ * per_cell_mu_lambda_host: NULL for the uniform (mu, lambda), else a host
+ * array of n_cells*2 doubles (mu, lambda per cell, cell index
+ * ex + nx*(ey + ny*ez)), copied.  Invalidates state-derived caches. */
+int mfe_set_material(mfe_ctx* ctx, double mu, double lambda,
+                     const double* per_cell_mu_lambda_host);
+
+/* Homogeneous Dirichlet constraints for the tangent: the listed dofs become
+ * identity rows and columns (apply reads w as 0 there and returns v_c = w_c;
+ * residual entries there are 0).  dofs_host: host array of n dof indices in
+ * [0, n_dofs), duplicates allowed; n = 0 clears the constraints. */
+int mfe_set_constraints(mfe_ctx* ctx, int64_t n, const int64_t* dofs_host);
+
+/* Set the linearisation point u (device array of n_dofs doubles, copied on
+ * `stream`).  Evaluates F = I + Grad u at every quadrature point and waits
+ * for the stream once to read the result: MFE_EJACOBIAN if det F <= 0
+ * anywhere (the state is then not set).  Marks every cache stale. */
+int mfe_set_state(mfe_ctx* ctx, const double* u_dev, void* stream);
+
+/* Build the per-quadrature-point data of `strategy` from the current state
+ * (Alg. 2 inputs): MFE_OTF_GEOM 10, MFE_T2 17, MFE_T4 36 doubles per point,
+ * structure-of-arrays, owned by the context.  No-op for MFE_OTF and
+ * MFE_OTF_AD.  MFE_ESTATE without a state.  Asynchronous on `stream`. */
+int mfe_build_cache(mfe_ctx* ctx, int strategy, void* stream);
+
+/* Bytes of device memory held for `strategy`'s cache (0 if not built). */
+int64_t mfe_cache_bytes(const mfe_ctx* ctx, int strategy);
+
+/* v = K(u) w with u the current state (Alg. 1 for MFE_OTF/MFE_OTF_GEOM/
+ * MFE_OTF_AD, Alg. 2 for MFE_T2/MFE_T4).  w_dev, v_dev: device arrays of
+ * n_dofs doubles; v is overwritten; w and v must not overlap (MFE_EINVAL).
+ * precision must be MFE_FP64.  MFE_ESTATE before set_state or when the
+ * strategy's cache was not built for the current state.  Asynchronous. */
+int mfe_apply_tangent(mfe_ctx* ctx, const void* w_dev, void* v_dev,
+                      int strategy, int precision, void* stream);
+
+/* r = residual of the weak form at displacement u (eq. F without traction):
+ * r_(a,i) = sum_cells sum_q JxW_q P_iA(F_q) Grad_A N_a, zero at constrained
+ * dofs.  u_dev, r_dev: device arrays of n_dofs doubles, must not overlap.
+ * Does not change the state.  Asynchronous (det F is not checked). */
+int mfe_residual(mfe_ctx* ctx, const double* u_dev, double* r_dev, void* stream);
+
+/* Average duration in milliseconds of the last `n` launches of the apply
+ * kernel recorded with timing enabled, measured by HIP events recorded
+ * around the kernel on the launch stream; -1 if none.  Timing is enabled by
+ * mfe_set_timing(ctx, 1) and costs two event records per apply. */
+int mfe_set_timing(mfe_ctx* ctx, int enabled);
+double mfe_apply_kernel_ms(mfe_ctx* ctx, int* count_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFE_H */

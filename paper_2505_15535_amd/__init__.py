@@ -1,0 +1,246 @@
+"""Python binding of libmfe (matrix-free finite-strain tangent on MI355X).
+
+Thin ctypes layer over the C ABI declared in ``include/mfe.h``: the module
+level functions have the same names and arguments as the C entry points
+(device buffers and streams are passed as integer addresses), and
+:class:`Operator` wraps a context for use with torch tensors.  Every step of
+the computation runs in the HIP kernels of ``libmfe.so``; this module only
+marshals arguments.  Importing it raises if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfe.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "mfe.h")
+
+# status codes
+MFE_OK, MFE_EINVAL, MFE_EHIP, MFE_ENOMEM, MFE_EJACOBIAN, MFE_ESTATE, MFE_ENOTCONV, MFE_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "MFE_OK", -1: "MFE_EINVAL", -2: "MFE_EHIP", -3: "MFE_ENOMEM", -4: "MFE_EJACOBIAN",
+                -5: "MFE_ESTATE", -6: "MFE_ENOTCONV", -7: "MFE_EUNSUPPORTED"}
+# strategies
+MFE_OTF, MFE_OTF_GEOM, MFE_T2, MFE_T4, MFE_OTF_AD = 0, 1, 2, 3, 4
+STRATEGIES = {"otf": MFE_OTF, "otf_geom": MFE_OTF_GEOM, "t2": MFE_T2, "t4": MFE_T4, "otf_ad": MFE_OTF_AD}
+# sweep precisions
+MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2505_15535_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+_SIGS = {
+    "mfe_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "mfe_destroy": (None, [_vp]),
+    "mfe_last_error": (ctypes.c_char_p, [_vp]),
+    "mfe_mesh_box": (_i, [_vp, _i, _i, _i, _i, _vp]),
+    "mfe_n_dofs": (_i64, [_vp]),
+    "mfe_n_cells": (_i64, [_vp]),
+    "mfe_n_qpoints": (_i64, [_vp]),
+    "mfe_set_material": (_i, [_vp, _d, _d, _vp]),
+    "mfe_set_constraints": (_i, [_vp, _i64, _vp]),
+    "mfe_set_state": (_i, [_vp, _vp, _vp]),
+    "mfe_build_cache": (_i, [_vp, _i, _vp]),
+    "mfe_cache_bytes": (_i64, [_vp, _i]),
+    "mfe_apply_tangent": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+    "mfe_residual": (_i, [_vp, _vp, _vp, _vp]),
+    "mfe_set_timing": (_i, [_vp, _i]),
+    "mfe_apply_kernel_ms": (_d, [_vp, ctypes.POINTER(_i)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_symbols(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions declared in the C header."""
+    with open(path) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfe_[a-z0-9_]+)\s*\(", text)))
+
+
+class MfeError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+# ----------------------------------------------------------------- raw ABI
+def mfe_create(hip_device: int = 0) -> int:
+    h = _vp()
+    rc = _lib.mfe_create(ctypes.byref(h), int(hip_device))
+    if rc != MFE_OK:
+        raise MfeError(rc, f"mfe_create(device={hip_device}) failed")
+    return h.value
+
+
+def mfe_destroy(ctx: int) -> None:
+    _lib.mfe_destroy(ctx)
+
+
+def mfe_last_error(ctx: int | None) -> str:
+    return (_lib.mfe_last_error(ctx) or b"").decode()
+
+
+def _check(ctx, rc):
+    if rc != MFE_OK:
+        raise MfeError(rc, mfe_last_error(ctx))
+    return rc
+
+
+def mfe_mesh_box(ctx, nx, ny, nz, degree, vertex_xyz_host_ptr):
+    return _check(ctx, _lib.mfe_mesh_box(ctx, nx, ny, nz, degree, vertex_xyz_host_ptr))
+
+
+def mfe_n_dofs(ctx) -> int:
+    return int(_lib.mfe_n_dofs(ctx))
+
+
+def mfe_n_cells(ctx) -> int:
+    return int(_lib.mfe_n_cells(ctx))
+
+
+def mfe_n_qpoints(ctx) -> int:
+    return int(_lib.mfe_n_qpoints(ctx))
+
+
+def mfe_set_material(ctx, mu, lam, per_cell_host_ptr=None):
+    return _check(ctx, _lib.mfe_set_material(ctx, float(mu), float(lam), per_cell_host_ptr))
+
+
+def mfe_set_constraints(ctx, n, dofs_host_ptr):
+    return _check(ctx, _lib.mfe_set_constraints(ctx, int(n), dofs_host_ptr))
+
+
+def mfe_set_state(ctx, u_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_set_state(ctx, u_dev_ptr, stream))
+
+
+def mfe_build_cache(ctx, strategy, stream=None):
+    return _check(ctx, _lib.mfe_build_cache(ctx, int(strategy), stream))
+
+
+def mfe_cache_bytes(ctx, strategy) -> int:
+    return int(_lib.mfe_cache_bytes(ctx, int(strategy)))
+
+
+def mfe_apply_tangent(ctx, w_dev_ptr, v_dev_ptr, strategy, precision=MFE_FP64, stream=None):
+    return _check(ctx, _lib.mfe_apply_tangent(ctx, w_dev_ptr, v_dev_ptr, int(strategy), int(precision), stream))
+
+
+def mfe_residual(ctx, u_dev_ptr, r_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_residual(ctx, u_dev_ptr, r_dev_ptr, stream))
+
+
+def mfe_set_timing(ctx, enabled: bool):
+    return _check(ctx, _lib.mfe_set_timing(ctx, 1 if enabled else 0))
+
+
+def mfe_apply_kernel_ms(ctx):
+    n = _i(0)
+    ms = _lib.mfe_apply_kernel_ms(ctx, ctypes.byref(n))
+    return float(ms), int(n.value)
+
+
+# ----------------------------------------------------------------- torch helper
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_f64(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 tensor of {n} entries")
+    return t.data_ptr()
+
+
+class Operator:
+    """A context holding one mesh, material, constraints, state and caches.
+
+    ``Operator(nx, ny, nz, degree, vertices, mu, lam)`` builds the mesh;
+    ``set_state(u)``, ``build_cache(strategy)``, ``apply(w, out, strategy)``
+    and ``residual(u, out)`` queue work on torch's current stream.
+    """
+
+    def __init__(self, nx, ny, nz, degree, vertices, mu=1.0, lam=1.0, per_cell=None, device=None):
+        import numpy as np
+        import torch
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = torch.device("cuda", dev)
+        self.ctx = mfe_create(dev)
+        verts = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1))
+        mfe_mesh_box(self.ctx, nx, ny, nz, degree, verts.ctypes.data)
+        self.n_dofs = mfe_n_dofs(self.ctx)
+        self.n_cells = mfe_n_cells(self.ctx)
+        self.n_qpoints = mfe_n_qpoints(self.ctx)
+        self.set_material(mu, lam, per_cell)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mfe_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_material(self, mu, lam, per_cell=None):
+        import numpy as np
+        if per_cell is None:
+            mfe_set_material(self.ctx, mu, lam, None)
+        else:
+            pc = np.ascontiguousarray(np.asarray(per_cell, dtype=np.float64).reshape(-1))
+            if pc.size != 2 * self.n_cells:
+                raise ValueError("per_cell must hold (mu, lambda) for every cell")
+            mfe_set_material(self.ctx, mu, lam, pc.ctypes.data)
+
+    def set_constraints(self, dofs):
+        import numpy as np
+        d = np.ascontiguousarray(np.asarray(dofs, dtype=np.int64).reshape(-1))
+        mfe_set_constraints(self.ctx, d.size, d.ctypes.data if d.size else None)
+
+    def set_state(self, u, stream=None):
+        mfe_set_state(self.ctx, _dev_f64(u, self.n_dofs, "u"), _stream_handle(stream))
+
+    def build_cache(self, strategy, stream=None):
+        mfe_build_cache(self.ctx, STRATEGIES.get(strategy, strategy), _stream_handle(stream))
+
+    def cache_bytes(self, strategy):
+        return mfe_cache_bytes(self.ctx, STRATEGIES.get(strategy, strategy))
+
+    def apply(self, w, out=None, strategy="otf", precision=MFE_FP64, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(w)
+        mfe_apply_tangent(self.ctx, _dev_f64(w, self.n_dofs, "w"), _dev_f64(out, self.n_dofs, "out"),
+                          STRATEGIES.get(strategy, strategy), precision, _stream_handle(stream))
+        return out
+
+    def residual(self, u, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(u)
+        mfe_residual(self.ctx, _dev_f64(u, self.n_dofs, "u"), _dev_f64(out, self.n_dofs, "out"),
+                     _stream_handle(stream))
+        return out
+
+    def set_timing(self, enabled=True):
+        mfe_set_timing(self.ctx, enabled)
+
+    def apply_kernel_ms(self):
+        return mfe_apply_kernel_ms(self.ctx)

@@ -1,0 +1,580 @@
+// C ABI of libmfe: context, mesh, material, constraints, state, caches,
+// tangent apply and residual.  Host-side 1D tables (Gauss rule, Gauss-Lobatto
+// support points, Lagrange matrices) are computed here.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mfe.h"
+#include "mfe_kernels.hpp"
+
+using mfe::KParams;
+using mfe::Tables1D;
+
+namespace {
+
+constexpr int kNumCaches = 3;  // OTF_GEOM, T2, T4
+int cache_slot(int strategy) {
+    switch (strategy) {
+        case MFE_OTF_GEOM: return 0;
+        case MFE_T2: return 1;
+        case MFE_T4: return 2;
+        default: return -1;
+    }
+}
+int cache_fields(int slot) {
+    return slot == 0 ? mfe::kGeomFields : (slot == 1 ? mfe::kT2Fields : mfe::kT4Fields);
+}
+
+// ----------------------------------------------------------------- 1D tables
+// Legendre polynomial P_n and its derivative at x in [-1, 1] (three-term recurrence).
+void legendre(int n, double x, double& P, double& dP) {
+    double p0 = 1.0, p1 = x;
+    if (n == 0) {
+        P = 1.0;
+        dP = 0.0;
+        return;
+    }
+    for (int k = 2; k <= n; ++k) {
+        const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+    }
+    P = p1;
+    dP = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+// n-point Gauss-Legendre rule on [0, 1] by Newton iteration on P_n.
+void gauss_rule(int n, double* x01, double* w01) {
+    std::vector<double> x(n), w(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(n, z, P, dP);
+            const double dz = P / dP;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        double P, dP;
+        legendre(n, z, P, dP);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dP * dP);
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return x[a] < x[b]; });
+    for (int i = 0; i < n; ++i) {
+        x01[i] = 0.5 * (x[order[i]] + 1.0);
+        w01[i] = 0.5 * w[order[i]];
+    }
+    // exact symmetry about 1/2
+    for (int i = 0; i < n / 2; ++i) {
+        const double a = 0.5 * (x01[i] + (1.0 - x01[n - 1 - i]));
+        x01[i] = a;
+        x01[n - 1 - i] = 1.0 - a;
+        const double b = 0.5 * (w01[i] + w01[n - 1 - i]);
+        w01[i] = w01[n - 1 - i] = b;
+    }
+    if (n % 2 == 1) x01[n / 2] = 0.5;
+}
+
+// Gauss-Lobatto-Legendre points of degree p on [0, 1]: end points and the
+// roots of P_p' (Newton on P_p' with P_p'' from Legendre's equation).
+void gll_points(int p, double* x01) {
+    std::vector<double> x(p + 1);
+    x[0] = -1.0;
+    x[p] = 1.0;
+    for (int i = 1; i < p; ++i) {
+        double z = -std::cos(M_PI * i / p);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(p, z, P, dP);
+            const double d2P = (2.0 * z * dP - p * (p + 1.0) * P) / (1.0 - z * z);
+            const double dz = dP / d2P;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[i] = z;
+    }
+    std::sort(x.begin(), x.end());
+    for (int i = 0; i <= p; ++i) x01[i] = 0.5 * (x[i] + 1.0);
+    for (int i = 0; i < (p + 1) / 2; ++i) {
+        const double a = 0.5 * (x01[i] + (1.0 - x01[p - i]));
+        x01[i] = a;
+        x01[p - i] = 1.0 - a;
+    }
+    if (p % 2 == 0) x01[p / 2] = 0.5;
+}
+
+void make_tables(int degree, Tables1D& t) {
+    const int n = degree + 1;
+    std::memset(&t, 0, sizeof(t));
+    t.n = n;
+    double nodes[8];
+    gll_points(degree, nodes);
+    gauss_rule(n, t.qp, t.qw);
+    // S[q][i] = l_i(x_q), Lagrange basis through the support points
+    for (int q = 0; q < n; ++q)
+        for (int i = 0; i < n; ++i) {
+            double v = 1.0;
+            for (int j = 0; j < n; ++j)
+                if (j != i) v *= (t.qp[q] - nodes[j]) / (nodes[i] - nodes[j]);
+            t.S[q][i] = v;
+        }
+    // D[q][l] = derivative at x_q of the Lagrange polynomial through the Gauss
+    // points that is 1 at x_l (barycentric form)
+    double bw[8];
+    for (int l = 0; l < n; ++l) {
+        double prod = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != l) prod *= (t.qp[l] - t.qp[m]);
+        bw[l] = 1.0 / prod;
+    }
+    for (int q = 0; q < n; ++q) {
+        double diag = 0.0;
+        for (int l = 0; l < n; ++l) {
+            if (l == q) continue;
+            t.D[q][l] = (bw[l] / bw[q]) / (t.qp[q] - t.qp[l]);
+            diag += 1.0 / (t.qp[q] - t.qp[l]);
+        }
+        t.D[q][q] = diag;
+    }
+    // enforce the exact centro-(anti)symmetry used by the even-odd sweeps
+    for (int q = 0; q < n; ++q)
+        for (int i = 0; i < n; ++i) {
+            const int q2 = n - 1 - q, i2 = n - 1 - i;
+            if (q * n + i > q2 * n + i2) continue;
+            const double s = 0.5 * (t.S[q][i] + t.S[q2][i2]);
+            t.S[q][i] = t.S[q2][i2] = s;
+            const double d = 0.5 * (t.D[q][i] - t.D[q2][i2]);
+            t.D[q][i] = d;
+            t.D[q2][i2] = -d;
+        }
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct mfe_ctx {
+    int device = 0;
+    std::string err;
+    // mesh
+    bool has_mesh = false;
+    int nx = 0, ny = 0, nz = 0, degree = 0;
+    int Nx = 0, Ny = 0, Nz = 0;
+    int64_t n_nodes = 0, n_dofs = 0, ne = 0, nq = 0;
+    Tables1D tab;
+    double* d_verts = nullptr;
+    // material
+    double mu = 1.0, lam = 1.0;
+    double* d_cellmat = nullptr;
+    // constraints
+    unsigned char* d_cmask = nullptr;
+    int64_t* d_cidx = nullptr;
+    int64_t n_con = 0;
+    // state and caches
+    double* d_u = nullptr;
+    bool has_state = false;
+    uint64_t state_version = 0;
+    double* d_cache[kNumCaches] = {nullptr, nullptr, nullptr};
+    uint64_t cache_version[kNumCaches] = {0, 0, 0};
+    bool cache_valid[kNumCaches] = {false, false, false};
+    int* d_flag = nullptr;
+    // timing of the apply kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    int ev_used = 0;
+};
+
+namespace {
+
+int fail(mfe_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(mfe_ctx* c, hipError_t e, const char* where) {
+    return fail(c, e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EHIP,
+                std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define MFE_HIP(ctx, call)                                  \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #call); \
+    } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_mesh_data(mfe_ctx* c) {
+    dfree(c->d_verts);
+    dfree(c->d_cellmat);
+    dfree(c->d_cmask);
+    dfree(c->d_cidx);
+    dfree(c->d_u);
+    for (int i = 0; i < kNumCaches; ++i) {
+        dfree(c->d_cache[i]);
+        c->cache_valid[i] = false;
+    }
+    c->n_con = 0;
+    c->has_state = false;
+    c->has_mesh = false;
+}
+
+KParams base_params(const mfe_ctx* c) {
+    KParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.nx = c->nx;
+    p.ny = c->ny;
+    p.nz = c->nz;
+    p.ne = (int)c->ne;
+    p.Nx = c->Nx;
+    p.Ny = c->Ny;
+    p.nq_total = c->nq;
+    p.verts = c->d_verts;
+    p.u = c->d_u;
+    p.cell_mat = c->d_cellmat;
+    p.mu = c->mu;
+    p.lam = c->lam;
+    p.cmask = c->n_con > 0 ? c->d_cmask : nullptr;
+    p.flag = c->d_flag;
+    return p;
+}
+
+bool overlaps(const void* a, const void* b, int64_t bytes) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfe_create(mfe_ctx** out, int hip_device) {
+    if (!out) return MFE_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count) return MFE_EINVAL;
+    mfe_ctx* c = new (std::nothrow) mfe_ctx();
+    if (!c) return MFE_ENOMEM;
+    c->device = hip_device;
+    DeviceGuard g(hip_device);
+    if (!g.ok || hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
+        delete c;
+        return MFE_EHIP;
+    }
+    *out = c;
+    return MFE_OK;
+}
+
+void mfe_destroy(mfe_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    free_mesh_data(c);
+    dfree(c->d_flag);
+    for (auto e : c->ev_start) (void)hipEventDestroy(e);
+    for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* mfe_last_error(const mfe_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* vxyz) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (nx < 1 || ny < 1 || nz < 1) return fail(c, MFE_EINVAL, "cell counts must be >= 1");
+    if (degree < 1 || degree > 6) return fail(c, MFE_EINVAL, "degree must be in 1..6");
+    if (!vxyz) return fail(c, MFE_EINVAL, "vertex array is null");
+    const int64_t Nx = (int64_t)degree * nx + 1, Ny = (int64_t)degree * ny + 1, Nz = (int64_t)degree * nz + 1;
+    const int64_t n_nodes = Nx * Ny * Nz;
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t nq = ne * (degree + 1) * (degree + 1) * (degree + 1);
+    if (3 * n_nodes >= (int64_t)1 << 31 || ne >= (int64_t)1 << 31)
+        return fail(c, MFE_EINVAL, "mesh too large for 32-bit dof indices");
+    // host-side check of det J_g > 0 at every Gauss point (trilinear map)
+    Tables1D t;
+    make_tables(degree, t);
+    const int n = degree + 1;
+    for (int64_t e = 0; e < ne; ++e) {
+        const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = (int)(e / ((int64_t)nx * ny));
+        double X[8][3];
+        for (int v = 0; v < 8; ++v) {
+            const int64_t id = (ex + (v & 1)) + (int64_t)(nx + 1) * ((ey + ((v >> 1) & 1)) + (int64_t)(ny + 1) * (ez + (v >> 2)));
+            for (int d = 0; d < 3; ++d) X[v][d] = vxyz[3 * id + d];
+        }
+        for (int qz = 0; qz < n; ++qz)
+            for (int qy = 0; qy < n; ++qy)
+                for (int qx = 0; qx < n; ++qx) {
+                    const double xi[3] = {t.qp[qx], t.qp[qy], t.qp[qz]};
+                    double J[3][3] = {};
+                    for (int v = 0; v < 8; ++v) {
+                        const int b[3] = {v & 1, (v >> 1) & 1, v >> 2};
+                        double f[3], df[3];
+                        for (int d = 0; d < 3; ++d) {
+                            f[d] = b[d] ? xi[d] : 1.0 - xi[d];
+                            df[d] = b[d] ? 1.0 : -1.0;
+                        }
+                        const double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+                        for (int d = 0; d < 3; ++d)
+                            for (int A = 0; A < 3; ++A) J[d][A] += X[v][d] * g[A];
+                    }
+                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    if (!(det > 0.0)) {
+                        char buf[160];
+                        std::snprintf(buf, sizeof(buf), "det J_g = %g <= 0 in cell %lld", det, (long long)e);
+                        return fail(c, MFE_EJACOBIAN, buf);
+                    }
+                }
+    }
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, MFE_EHIP, "hipSetDevice failed");
+    MFE_HIP(c, hipDeviceSynchronize());
+    free_mesh_data(c);
+    const int64_t nv = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    MFE_HIP(c, hipMalloc(&c->d_verts, nv * 3 * sizeof(double)));
+    MFE_HIP(c, hipMemcpy(c->d_verts, vxyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_u, 3 * n_nodes * sizeof(double)));
+    MFE_HIP(c, hipMalloc(&c->d_cmask, 3 * n_nodes));
+    MFE_HIP(c, hipMemset(c->d_cmask, 0, 3 * n_nodes));
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->degree = degree;
+    c->Nx = (int)Nx;
+    c->Ny = (int)Ny;
+    c->Nz = (int)Nz;
+    c->n_nodes = n_nodes;
+    c->n_dofs = 3 * n_nodes;
+    c->ne = ne;
+    c->nq = nq;
+    c->tab = t;
+    c->mu = 1.0;
+    c->lam = 1.0;
+    c->has_mesh = true;
+    return MFE_OK;
+}
+
+int64_t mfe_n_dofs(const mfe_ctx* c) { return (c && c->has_mesh) ? c->n_dofs : 0; }
+int64_t mfe_n_cells(const mfe_ctx* c) { return (c && c->has_mesh) ? c->ne : 0; }
+int64_t mfe_n_qpoints(const mfe_ctx* c) { return (c && c->has_mesh) ? c->nq : 0; }
+
+int mfe_set_material(mfe_ctx* c, double mu, double lam, const double* per_cell) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!std::isfinite(mu) || !std::isfinite(lam)) return fail(c, MFE_EINVAL, "non-finite material");
+    DeviceGuard g(c->device);
+    MFE_HIP(c, hipDeviceSynchronize());
+    dfree(c->d_cellmat);
+    if (per_cell) {
+        MFE_HIP(c, hipMalloc(&c->d_cellmat, c->ne * 2 * sizeof(double)));
+        MFE_HIP(c, hipMemcpy(c->d_cellmat, per_cell, c->ne * 2 * sizeof(double), hipMemcpyHostToDevice));
+    }
+    c->mu = mu;
+    c->lam = lam;
+    c->cache_valid[1] = c->cache_valid[2] = false;  // material enters T2/T4
+    return MFE_OK;
+}
+
+int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (n < 0 || (n > 0 && !dofs)) return fail(c, MFE_EINVAL, "bad constraint list");
+    std::vector<unsigned char> mask(c->n_dofs, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (dofs[i] < 0 || dofs[i] >= c->n_dofs) return fail(c, MFE_EINVAL, "constrained dof out of range");
+        mask[dofs[i]] = 1;
+    }
+    std::vector<int64_t> idx;
+    for (int64_t i = 0; i < c->n_dofs; ++i)
+        if (mask[i]) idx.push_back(i);
+    DeviceGuard g(c->device);
+    MFE_HIP(c, hipDeviceSynchronize());
+    dfree(c->d_cidx);
+    MFE_HIP(c, hipMemcpy(c->d_cmask, mask.data(), c->n_dofs, hipMemcpyHostToDevice));
+    if (!idx.empty()) {
+        MFE_HIP(c, hipMalloc(&c->d_cidx, idx.size() * sizeof(int64_t)));
+        MFE_HIP(c, hipMemcpy(c->d_cidx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    c->n_con = (int64_t)idx.size();
+    return MFE_OK;
+}
+
+int mfe_set_state(mfe_ctx* c, const double* u, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!u) return fail(c, MFE_EINVAL, "u is null");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MFE_HIP(c, hipMemcpyAsync(c->d_u, u, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MFE_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+    KParams p = base_params(c);
+    p.cmask = nullptr;  // the state is taken as given, constraints included
+    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_STATE, c->tab, p, s));
+    int flag = 0;
+    MFE_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipStreamSynchronize(s));
+    c->state_version++;
+    c->cache_valid[1] = c->cache_valid[2] = false;
+    if (flag) {
+        c->has_state = false;
+        return fail(c, MFE_EJACOBIAN, "det F <= 0 at some quadrature point");
+    }
+    c->has_state = true;
+    return MFE_OK;
+}
+
+int mfe_build_cache(mfe_ctx* c, int strategy, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (strategy == MFE_OTF || strategy == MFE_OTF_AD) return MFE_OK;
+    const int slot = cache_slot(strategy);
+    if (slot < 0) return fail(c, MFE_EINVAL, "unknown strategy");
+    if (slot > 0 && !c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!c->d_cache[slot]) MFE_HIP(c, hipMalloc(&c->d_cache[slot], (size_t)cache_fields(slot) * c->nq * sizeof(double)));
+    KParams p = base_params(c);
+    p.cmask = nullptr;
+    p.cache_out = c->d_cache[slot];
+    const int mode = slot == 0 ? mfe::MODE_BUILD_GEOM : (slot == 1 ? mfe::MODE_BUILD_T2 : mfe::MODE_BUILD_T4);
+    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s));
+    c->cache_valid[slot] = true;
+    c->cache_version[slot] = c->state_version;
+    return MFE_OK;
+}
+
+int64_t mfe_cache_bytes(const mfe_ctx* c, int strategy) {
+    if (!c || !c->has_mesh) return 0;
+    const int slot = cache_slot(strategy);
+    if (slot < 0 || !c->d_cache[slot]) return 0;
+    return (int64_t)cache_fields(slot) * c->nq * (int64_t)sizeof(double);
+}
+
+int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int precision, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!w || !v) return fail(c, MFE_EINVAL, "null vector");
+    if (overlaps(w, v, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "w and v overlap");
+    if (precision != MFE_FP64) {
+        if (precision >= MFE_SF_FP32 && precision <= MFE_SF_BF16X3)
+            return fail(c, MFE_EUNSUPPORTED, "mixed-precision sweeps are not built");
+        return fail(c, MFE_EINVAL, "unknown precision");
+    }
+    int mode;
+    switch (strategy) {
+        case MFE_OTF: mode = mfe::MODE_APPLY_OTF; break;
+        case MFE_OTF_GEOM: mode = mfe::MODE_APPLY_OTF_GEOM; break;
+        case MFE_T2: mode = mfe::MODE_APPLY_T2; break;
+        case MFE_T4: mode = mfe::MODE_APPLY_T4; break;
+        case MFE_OTF_AD: mode = mfe::MODE_APPLY_OTF_AD; break;
+        default: return fail(c, MFE_EINVAL, "unknown strategy");
+    }
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    const int slot = cache_slot(strategy);
+    if (slot >= 0) {
+        if (!c->cache_valid[slot] || (slot > 0 && c->cache_version[slot] != c->state_version))
+            return fail(c, MFE_ESTATE, "cache not built for the current state");
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams p = base_params(c);
+    p.w = static_cast<const double*>(w);
+    p.v = static_cast<double*>(v);
+    p.cache = slot >= 0 ? c->d_cache[slot] : nullptr;
+    MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
+    const bool timed = c->timing;
+    if (timed) {
+        if (c->ev_used == (int)c->ev_start.size()) {
+            hipEvent_t a, b;
+            MFE_HIP(c, hipEventCreate(&a));
+            MFE_HIP(c, hipEventCreate(&b));
+            c->ev_start.push_back(a);
+            c->ev_stop.push_back(b);
+        }
+        MFE_HIP(c, hipEventRecord(c->ev_start[c->ev_used], s));
+    }
+    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s));
+    if (timed) {
+        MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
+        c->ev_used++;
+    }
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, p.w, p.v, s));
+    return MFE_OK;
+}
+
+int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!u || !r) return fail(c, MFE_EINVAL, "null vector");
+    if (overlaps(u, r, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "u and r overlap");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams p = base_params(c);
+    p.u = u;
+    p.cmask = nullptr;  // constraints act on the rows only, via the zeroing below
+    p.v = r;
+    MFE_HIP(c, mfe::launch_fill(r, c->n_dofs, 0.0, s));
+    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_RESIDUAL, c->tab, p, s));
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_zero_indexed(c->d_cidx, c->n_con, r, s));
+    return MFE_OK;
+}
+
+int mfe_set_timing(mfe_ctx* c, int enabled) {
+    if (!c) return MFE_EINVAL;
+    c->timing = enabled != 0;
+    c->ev_used = 0;
+    return MFE_OK;
+}
+
+double mfe_apply_kernel_ms(mfe_ctx* c, int* count_out) {
+    if (count_out) *count_out = 0;
+    if (!c || c->ev_used == 0) return -1.0;
+    DeviceGuard g(c->device);
+    double total = 0.0;
+    for (int i = 0; i < c->ev_used; ++i) {
+        if (hipEventSynchronize(c->ev_stop[i]) != hipSuccess) return -1.0;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]) != hipSuccess) return -1.0;
+        total += ms;
+    }
+    if (count_out) *count_out = c->ev_used;
+    return total / c->ev_used;
+}
+
+}  // extern "C"

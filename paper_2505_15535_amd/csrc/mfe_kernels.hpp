@@ -1,0 +1,65 @@
+// Host-visible declarations of the HIP kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mfe {
+
+// What a launch of the cell kernel computes.
+enum Mode : int {
+    MODE_APPLY_OTF = 0,       // v += K(u) w, geometry from vertices, closed form
+    MODE_APPLY_OTF_GEOM = 1,  // v += K(u) w, stored inverse Jacobian and JxW
+    MODE_APPLY_T2 = 2,        // v += K w from the second-order cache
+    MODE_APPLY_T4 = 3,        // v += K w from the fourth-order cache
+    MODE_APPLY_OTF_AD = 4,    // v += K(u) w, dual-number directional derivative
+    MODE_RESIDUAL = 5,        // v += R(u)
+    MODE_STATE = 6,           // flag det F <= 0
+    MODE_BUILD_GEOM = 7,      // cache <- (Jg^-1, JxW)
+    MODE_BUILD_T2 = 8,        // cache <- (M, tau JxW, c1, c2)
+    MODE_BUILD_T4 = 9,        // cache <- (Jc JxW, tau JxW, M)
+    MODE_COUNT = 10
+};
+
+// Doubles per quadrature point of each cache.
+constexpr int kGeomFields = 10;
+constexpr int kT2Fields = 17;
+constexpr int kT4Fields = 36;
+
+struct KParams {
+    int nx, ny, nz;            // cells per direction
+    int ne;                    // nx*ny*nz
+    int Nx, Ny;                // nodes per direction (x, y)
+    int64_t nq_total;          // ne * (p+1)^3, stride between cache fields
+    const double* verts;       // (nx+1)(ny+1)(nz+1) x 3
+    const double* u;           // state (gather source of the u field)
+    const double* w;           // input vector (gather source of the w field)
+    double* v;                 // output, accumulated with atomics
+    const double* cache;       // SoA cache read by OTF_GEOM/T2/T4 applies
+    double* cache_out;         // SoA cache written by BUILD modes
+    const double* cell_mat;    // ne x (mu, lambda) or null
+    double mu, lam;            // uniform material
+    const unsigned char* cmask;  // per-dof constraint mask or null
+    int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
+};
+
+// 1D data of degree p = N-1 computed on the host: S (Lagrange basis on
+// Gauss-Lobatto support points, evaluated at Gauss points), D (derivative
+// collocated on the Gauss points), Gauss points and weights on [0, 1].
+struct Tables1D {
+    int n;
+    double S[8][8];
+    double D[8][8];
+    double qp[8];
+    double qw[8];
+};
+
+// Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).
+hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream);
+
+hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream);
+hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
+                               hipStream_t stream);
+hipError_t launch_zero_indexed(const int64_t* idx, int64_t n, double* dst, hipStream_t stream);
+
+}  // namespace mfe
