@@ -32,6 +32,11 @@ MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2505_15535_amd/build.py)")
 
+# torch owns the process's HIP runtime; loading it first makes libmfe bind to
+# that same runtime (matching soname) instead of a second copy from /opt/rocm,
+# which would put two HIP/HSA runtimes in one process.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
 

@@ -47,8 +47,9 @@ __device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& ex,
 // Forward sweeps of one vector field (3 components) of the batch.
 // On exit: sG[((e*N3 + q)*3 + c)*3 + d] = d field_c / d xi_d at point q.
 // Uses sA, sB as scratch.  Must be called by every thread of the block.
+// MASK: read constrained dofs as zero (the input w of the tangent, not u).
 // ---------------------------------------------------------------------------
-template <int N, int NT>
+template <int N, int NT, bool MASK>
 __device__ __forceinline__ void forward_sweeps(const double* __restrict__ src, const KParams& p,
                                                int cell0, int nE, const Tables<N>& T,
                                                double* sA, double* sB, double* sG) {
@@ -70,7 +71,7 @@ __device__ __forceinline__ void forward_sweeps(const double* __restrict__ src, c
         for (int i = 0; i < N; ++i) {
             const int dof = 3 * (base + i) + c;
             double val = src[dof];
-            if (p.cmask != nullptr && p.cmask[dof]) val = 0.0;
+            if (MASK && p.cmask != nullptr && p.cmask[dof]) val = 0.0;
             x[i] = val;
         }
         apply_eo<N, false>(T.S, x, y);
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
     double F[3][3] = {};
     double du[3][3] = {};
     if constexpr (MI::fwd_u) {
-        forward_sweeps<N, NT>(p.u, p, cell0, nE, T, sA, sB, sG);
+        forward_sweeps<N, NT, false>(p.u, p, cell0, nE, T, sA, sB, sG);
         if (active) {
             load_grad<N>(sG, el, q, du);
             if constexpr (MODE == MODE_APPLY_OTF_GEOM) {
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
     double Q[3][3] = {};
     if constexpr (MI::fwd_w) {
         if constexpr (!MI::fwd_u) __syncthreads();  // edge table (unused) / uniform entry
-        forward_sweeps<N, NT>(p.w, p, cell0, nE, T, sA, sB, sG);
+        forward_sweeps<N, NT, true>(p.w, p, cell0, nE, T, sA, sB, sG);
         if (active) {
             double dw[3][3];
             load_grad<N>(sG, el, q, dw);
