@@ -134,6 +134,8 @@ def main(argv=None):
     ap.add_argument("--strategies", default=",".join(STRATEGIES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (reference for HBM counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -158,6 +160,16 @@ def main(argv=None):
     v = torch.empty_like(w)
     print(f"[bench] {cfg.name}: {op.n_dofs} dofs, {op.n_cells} cells, {op.n_qpoints} points", file=sys.stderr,
           flush=True)
+
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copies: 3 x {args.calibrate_copy_mib} MiB", file=sys.stderr, flush=True)
+        del src, dst
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()

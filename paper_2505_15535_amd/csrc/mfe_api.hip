@@ -182,13 +182,15 @@ struct mfe_ctx {
     int nx = 0, ny = 0, nz = 0, degree = 0;
     int Nx = 0, Ny = 0, Nz = 0;
     int64_t n_nodes = 0, n_dofs = 0, ne = 0, nq = 0;
+    int nbx = 0, nby = 0, nbz = 0;  // bricks per direction
+    int64_t nq_stride = 0;          // cache entries per field (bricks * points per brick)
     Tables1D tab;
     double* d_verts = nullptr;
     // material
     double mu = 1.0, lam = 1.0;
     double* d_cellmat = nullptr;
     // constraints
-    unsigned char* d_cmask = nullptr;
+    double* d_wmask = nullptr;   // w with constrained entries zeroed
     int64_t* d_cidx = nullptr;
     int64_t n_con = 0;
     // state and caches
@@ -232,7 +234,7 @@ void dfree(T*& p) {
 void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_verts);
     dfree(c->d_cellmat);
-    dfree(c->d_cmask);
+    dfree(c->d_wmask);
     dfree(c->d_cidx);
     dfree(c->d_u);
     for (int i = 0; i < kNumCaches; ++i) {
@@ -253,13 +255,15 @@ KParams base_params(const mfe_ctx* c) {
     p.ne = (int)c->ne;
     p.Nx = c->Nx;
     p.Ny = c->Ny;
-    p.nq_total = c->nq;
+    p.nbx = c->nbx;
+    p.nby = c->nby;
+    p.nbz = c->nbz;
+    p.nq_stride = c->nq_stride;
     p.verts = c->d_verts;
     p.u = c->d_u;
     p.cell_mat = c->d_cellmat;
     p.mu = c->mu;
     p.lam = c->lam;
-    p.cmask = c->n_con > 0 ? c->d_cmask : nullptr;
     p.flag = c->d_flag;
     return p;
 }
@@ -364,8 +368,6 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
     MFE_HIP(c, hipMalloc(&c->d_verts, nv * 3 * sizeof(double)));
     MFE_HIP(c, hipMemcpy(c->d_verts, vxyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice));
     MFE_HIP(c, hipMalloc(&c->d_u, 3 * n_nodes * sizeof(double)));
-    MFE_HIP(c, hipMalloc(&c->d_cmask, 3 * n_nodes));
-    MFE_HIP(c, hipMemset(c->d_cmask, 0, 3 * n_nodes));
     c->nx = nx;
     c->ny = ny;
     c->nz = nz;
@@ -377,6 +379,12 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
     c->n_dofs = 3 * n_nodes;
     c->ne = ne;
     c->nq = nq;
+    int bx, by, bz, ppb;
+    mfe::brick_shape(degree + 1, &bx, &by, &bz, &ppb);
+    c->nbx = (nx + bx - 1) / bx;
+    c->nby = (ny + by - 1) / by;
+    c->nbz = (nz + bz - 1) / bz;
+    c->nq_stride = (int64_t)c->nbx * c->nby * c->nbz * ppb;
     c->tab = t;
     c->mu = 1.0;
     c->lam = 1.0;
@@ -422,8 +430,9 @@ int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
     DeviceGuard g(c->device);
     MFE_HIP(c, hipDeviceSynchronize());
     dfree(c->d_cidx);
-    MFE_HIP(c, hipMemcpy(c->d_cmask, mask.data(), c->n_dofs, hipMemcpyHostToDevice));
+    dfree(c->d_wmask);
     if (!idx.empty()) {
+        MFE_HIP(c, hipMalloc(&c->d_wmask, c->n_dofs * sizeof(double)));
         MFE_HIP(c, hipMalloc(&c->d_cidx, idx.size() * sizeof(int64_t)));
         MFE_HIP(c, hipMemcpy(c->d_cidx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     }
@@ -441,7 +450,6 @@ int mfe_set_state(mfe_ctx* c, const double* u, void* stream) {
     MFE_HIP(c, hipMemcpyAsync(c->d_u, u, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
     MFE_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
     KParams p = base_params(c);
-    p.cmask = nullptr;  // the state is taken as given, constraints included
     MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_STATE, c->tab, p, s));
     int flag = 0;
     MFE_HIP(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -466,9 +474,8 @@ int mfe_build_cache(mfe_ctx* c, int strategy, void* stream) {
     if (slot > 0 && !c->has_state) return fail(c, MFE_ESTATE, "no state set");
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!c->d_cache[slot]) MFE_HIP(c, hipMalloc(&c->d_cache[slot], (size_t)cache_fields(slot) * c->nq * sizeof(double)));
+    if (!c->d_cache[slot]) MFE_HIP(c, hipMalloc(&c->d_cache[slot], (size_t)cache_fields(slot) * c->nq_stride * sizeof(double)));
     KParams p = base_params(c);
-    p.cmask = nullptr;
     p.cache_out = c->d_cache[slot];
     const int mode = slot == 0 ? mfe::MODE_BUILD_GEOM : (slot == 1 ? mfe::MODE_BUILD_T2 : mfe::MODE_BUILD_T4);
     MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s));
@@ -481,7 +488,7 @@ int64_t mfe_cache_bytes(const mfe_ctx* c, int strategy) {
     if (!c || !c->has_mesh) return 0;
     const int slot = cache_slot(strategy);
     if (slot < 0 || !c->d_cache[slot]) return 0;
-    return (int64_t)cache_fields(slot) * c->nq * (int64_t)sizeof(double);
+    return (int64_t)cache_fields(slot) * c->nq_stride * (int64_t)sizeof(double);
 }
 
 int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int precision, void* stream) {
@@ -516,6 +523,11 @@ int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     p.w = static_cast<const double*>(w);
     p.v = static_cast<double*>(v);
     p.cache = slot >= 0 ? c->d_cache[slot] : nullptr;
+    if (c->n_con > 0) {  // the kernel reads w with the constrained entries zeroed
+        MFE_HIP(c, hipMemcpyAsync(c->d_wmask, w, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+        MFE_HIP(c, mfe::launch_zero_indexed(c->d_cidx, c->n_con, c->d_wmask, s));
+        p.w = c->d_wmask;
+    }
     MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
     const bool timed = c->timing;
     if (timed) {
@@ -533,7 +545,8 @@ int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
         c->ev_used++;
     }
-    if (c->n_con > 0) MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, p.w, p.v, s));
+    if (c->n_con > 0)
+        MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const double*>(w), p.v, s));
     return MFE_OK;
 }
 
@@ -547,7 +560,6 @@ int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     KParams p = base_params(c);
     p.u = u;
-    p.cmask = nullptr;  // constraints act on the rows only, via the zeroing below
     p.v = r;
     MFE_HIP(c, mfe::launch_fill(r, c->n_dofs, 0.0, s));
     MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_RESIDUAL, c->tab, p, s));

@@ -1,13 +1,15 @@
 // Cell kernels of the matrix-free tangent, residual, state check and cache
 // construction on gfx950 (FP64).
 //
-// One workgroup processes a batch of E consecutive cells (x fastest), with
-// one thread per quadrature point of the batch for the point-wise work
-// (Alg. 1/Alg. 2 quadrature loop) and one thread per 1D line ("pencil") of a
-// component for each sum-factorization sweep (Sec. 2.4).  Intermediate
-// tensors are staged in LDS; sweeps between stages are separated by
-// workgroup barriers.  The scatter-add into the global result uses hardware
-// FP64 atomics.
+// One workgroup processes a brick of neighbouring cells (4x2x2 for Q2), with
+// one thread per quadrature point of the brick for the point-wise work
+// (Alg. 1/Alg. 2 quadrature loop) and one thread per 1D line of a component
+// for each sum-factorization sweep (Sec. 2.4).  The brick's nodal values are
+// gathered once with coalesced row loads into LDS; intermediate tensors are
+// staged in LDS with workgroup barriers between sweep stages.  The cells'
+// contributions are summed in LDS, then written with plain stores for nodes
+// inside the brick and FP64 atomics for nodes on its faces.  Per-point caches
+// are stored brick-major so that a workgroup streams one contiguous range.
 //
 // Sum factorization (collocation form): nodal values are interpolated to the
 // Gauss points with three sweeps of S (x, y, z), then the reference gradient
@@ -19,245 +21,354 @@
 
 namespace mfe {
 
-template <int N>
-struct Cfg;
-template <> struct Cfg<2> { static constexpr int E = 32, NT = 256; };
-template <> struct Cfg<3> { static constexpr int E = 7, NT = 192; };
-template <> struct Cfg<4> { static constexpr int E = 4, NT = 256; };
-template <> struct Cfg<5> { static constexpr int E = 2, NT = 256; };
-template <> struct Cfg<6> { static constexpr int E = 1, NT = 256; };
-template <> struct Cfg<7> { static constexpr int E = 1, NT = 384; };
+// Bricks: a workgroup owns BX x BY x BZ neighbouring cells of the box.  The
+// Q2 shape can be chosen at build time (cells per direction).
+#ifndef MFE_Q2_BRICK_X
+#define MFE_Q2_BRICK_X 3
+#endif
+#ifndef MFE_Q2_BRICK_Y
+#define MFE_Q2_BRICK_Y 3
+#endif
+#ifndef MFE_Q2_BRICK_Z
+#define MFE_Q2_BRICK_Z 1
+#endif
+template <int N> struct BrickDims;
+template <> struct BrickDims<2> { static constexpr int BX = 4, BY = 4, BZ = 2; };
+template <> struct BrickDims<3> {
+    static constexpr int BX = MFE_Q2_BRICK_X, BY = MFE_Q2_BRICK_Y, BZ = MFE_Q2_BRICK_Z;
+};
+template <> struct BrickDims<4> { static constexpr int BX = 2, BY = 2, BZ = 1; };
+template <> struct BrickDims<5> { static constexpr int BX = 2, BY = 1, BZ = 1; };
+template <> struct BrickDims<6> { static constexpr int BX = 1, BY = 1, BZ = 1; };
+template <> struct BrickDims<7> { static constexpr int BX = 1, BY = 1, BZ = 1; };
 
-// Map the hardware block index to a batch index so that each of the 8 XCDs
+template <int N>
+struct Geo {
+    static constexpr int P = N - 1, N2 = N * N, N3 = N2 * N;
+    static constexpr int BX = BrickDims<N>::BX, BY = BrickDims<N>::BY, BZ = BrickDims<N>::BZ;
+    static constexpr int CPB = BX * BY * BZ;               // cells per brick
+    static constexpr int NQ = CPB * N3;                    // quadrature points per brick
+    static constexpr int NT = (NQ + 63) / 64 * 64;         // threads: one per point
+    static constexpr int TASKS = 3 * N2 * CPB;             // 1D lines per sweep stage
+    static constexpr int TPT = (TASKS + NT - 1) / NT;      // lines per thread
+    static constexpr int GX = P * BX + 1, GY = P * BY + 1, GZ = P * BZ + 1;  // brick nodes
+    static constexpr int ROW = 3 * GX;                     // doubles in a brick node row
+    static constexpr int BRICK = ROW * GY * GZ;            // doubles of the brick node array
+    static constexpr int GPT = (BRICK + NT - 1) / NT;      // brick entries per thread
+};
+
+// Map the hardware block index to a brick index so that each of the 8 XCDs
 // (blocks are dealt round-robin to them) works on one contiguous range of
-// cells and neighbouring cells share that XCD's L2.
-__device__ __forceinline__ int xcd_batch(int b, int nb) {
+// bricks and neighbouring bricks share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-__device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& ex, int& ey, int& ez) {
-    ex = cell % p.nx;
-    const int r = cell / p.nx;
-    ey = r % p.ny;
-    ez = r / p.ny;
+// Position of the workgroup's brick and which of its cells exist.
+struct BrickPos {
+    int brick;
+    int ex0, ey0, ez0;     // first cell
+    int ncx, ncy, ncz;     // existing cells per direction
+    int node0;             // global index of the brick's first node
+};
+
+__device__ __forceinline__ BrickPos brick_pos(const KParams& p, int BX, int BY, int BZ, int P) {
+    BrickPos b;
+    b.brick = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = b.brick % p.nbx, r = b.brick / p.nbx;
+    const int by = r % p.nby, bz = r / p.nby;
+    b.ex0 = bx * BX;
+    b.ey0 = by * BY;
+    b.ez0 = bz * BZ;
+    b.ncx = min(BX, p.nx - b.ex0);
+    b.ncy = min(BY, p.ny - b.ey0);
+    b.ncz = min(BZ, p.nz - b.ez0);
+    b.node0 = P * b.ex0 + p.Nx * (P * b.ey0 + p.Ny * P * b.ez0);
+    return b;
+}
+
+// One 1D line of a sweep stage: component c, line coordinates (a, b) and
+// brick-local cell lc = lx + BX*(ly + BY*lz).
+struct Line {
+    int c, a, b, lc, lx, ly, lz;
+    bool valid;
+};
+
+template <int N>
+__device__ __forceinline__ Line line_of(int t, const BrickPos& bp) {
+    using G = Geo<N>;
+    Line L;
+    L.c = t % 3;
+    const int r = t / 3;
+    L.a = r % N;
+    L.b = (r / N) % N;
+    L.lc = r / G::N2;
+    L.lx = L.lc % G::BX;
+    L.ly = (L.lc / G::BX) % G::BY;
+    L.lz = L.lc / (G::BX * G::BY);
+    L.valid = t < G::TASKS && L.lx < bp.ncx && L.ly < bp.ncy && L.lz < bp.ncz;
+    return L;
+}
+
+// The brick node array entries handled by this thread: entry
+// e = tid + k*NT is (node row, offset) = (e / ROW, e % ROW) with the x-row of
+// the brick's nodes contiguous, exactly as in the global vector.
+template <int N>
+struct BrickMap {
+    int dof[Geo<N>::GPT];
+    unsigned exists;   // bit k: entry k is a node of an existing cell
+    unsigned face;     // bit k: that node lies on a face of the brick
+};
+
+template <int N>
+__device__ __forceinline__ BrickMap<N> brick_map(const KParams& p, const BrickPos& bp) {
+    using G = Geo<N>;
+    BrickMap<N> m;
+    m.exists = 0u;
+    m.face = 0u;
+#pragma unroll
+    for (int k = 0; k < G::GPT; ++k) {
+        const int e = threadIdx.x + k * G::NT;
+        const int row = e / G::ROW;
+        const int off = e - row * G::ROW;
+        const int jr = row % G::GY, kr = row / G::GY;
+        const int i = off / 3;
+        const bool ex = e < G::BRICK && i <= G::P * bp.ncx && jr <= G::P * bp.ncy && kr <= G::P * bp.ncz;
+        m.dof[k] = 3 * (bp.node0 + p.Nx * (jr + p.Ny * kr)) + off;
+        if (ex) m.exists |= 1u << k;
+        if (i == 0 || i == G::GX - 1 || jr == 0 || jr == G::GY - 1 || kr == 0 || kr == G::GZ - 1)
+            m.face |= 1u << k;
+    }
+    return m;
+}
+
+template <int N>
+__device__ __forceinline__ void brick_load(const double* __restrict__ src, const BrickMap<N>& m,
+                                           double (&r)[Geo<N>::GPT]) {
+#pragma unroll
+    for (int k = 0; k < Geo<N>::GPT; ++k) r[k] = (m.exists >> k & 1u) ? src[m.dof[k]] : 0.0;
+}
+
+template <int N>
+__device__ __forceinline__ void brick_store(double* sBrick, const double (&r)[Geo<N>::GPT]) {
+#pragma unroll
+    for (int k = 0; k < Geo<N>::GPT; ++k) {
+        const int e = threadIdx.x + k * Geo<N>::NT;
+        if (e < Geo<N>::BRICK) sBrick[e] = r[k];
+    }
+}
+
+// LDS layout.  sG holds 9 doubles per quadrature point, addressed as
+// slot s of component c at point idx of cell lc:  ((lc*N3 + idx)*3 + c)*3 + s.
+// The sweep stages pass their intermediate tensors through the three slots;
+// after the forward sweeps slot d holds d field_c / d xi_d, before the
+// backward sweeps slot d holds Q[c][d].  sV holds 3 doubles per point
+// ((lc*N3 + idx)*3 + c): the values at the Gauss points, then scratch of the
+// backward sweeps.
+template <int N>
+__device__ __forceinline__ int gofs(int lc, int idx, int c) {
+    return ((lc * Geo<N>::N3 + idx) * 3 + c) * 3;
 }
 
 // ---------------------------------------------------------------------------
-// Forward sweeps of one vector field (3 components) of the batch.
-// On exit: sG[((e*N3 + q)*3 + c)*3 + d] = d field_c / d xi_d at point q.
-// Uses sA, sB as scratch.  Must be called by every thread of the block.
-// MASK: read constrained dofs as zero (the input w of the tangent, not u).
+// Forward sweeps of one vector field whose brick nodal values are in sBrick
+// (made visible by a barrier before the call).  On exit slot d of sG holds
+// the reference gradient d field_c / d xi_d at every point.
 // ---------------------------------------------------------------------------
-template <int N, int NT, bool MASK>
-__device__ __forceinline__ void forward_sweeps(const double* __restrict__ src, const KParams& p,
-                                               int cell0, int nE, const Tables<N>& T,
-                                               double* sA, double* sB, double* sG) {
-    constexpr int N2 = N * N, N3 = N2 * N, P = N - 1;
-    const int tid = threadIdx.x;
-    // x: gather an x-row of nodal values, interpolate along x
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int j = r % N;
-        r /= N;
-        const int k = r % N;
-        const int e = r / N;
-        int ex, ey, ez;
-        cell_coords(p, cell0 + e, ex, ey, ez);
-        const int base = P * ex + p.Nx * ((P * ey + j) + p.Ny * (P * ez + k));
+template <int N>
+__device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<N>& T, double* sG,
+                                               double* sV, double* sBrick, bool clear_brick) {
+    using G = Geo<N>;
+    constexpr int N2 = G::N2, P = G::P;
+    // x: interpolate every cell's node x-rows -> slot 0 at (qx, j, k)
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int j = L.a, k = L.b;
+        const double* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
         double x[N], y[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const int dof = 3 * (base + i) + c;
-            double val = src[dof];
-            if (MASK && p.cmask != nullptr && p.cmask[dof]) val = 0.0;
-            x[i] = val;
-        }
+        for (int i = 0; i < N; ++i) x[i] = row[3 * i];
         apply_eo<N, false>(T.S, x, y);
+        double* out = sG + gofs<N>(L.lc, N * (j + N * k), L.c);
 #pragma unroll
-        for (int qx = 0; qx < N; ++qx) sA[(e * N3 + qx + N * (j + N * k)) * 3 + c] = y[qx];
+        for (int qx = 0; qx < N; ++qx) out[9 * qx] = y[qx];
     }
     __syncthreads();
-    // y: interpolate along y
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int qx = r % N;
-        r /= N;
-        const int k = r % N;
-        const int e = r / N;
+    // the brick array is free again: clear it for the backward accumulation
+    if (clear_brick)
+        for (int e = threadIdx.x; e < G::BRICK; e += G::NT) sBrick[e] = 0.0;
+    // y: slot 0 at (qx, j, k) -> slot 1 at (qx, qy, k)
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
         double x[N], y[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sA[(e * N3 + qx + N * (j + N * k)) * 3 + c];
+        for (int j = 0; j < N; ++j) x[j] = sG[base + 9 * N * j];
         apply_eo<N, false>(T.S, x, y);
 #pragma unroll
-        for (int qy = 0; qy < N; ++qy) sB[(e * N3 + qx + N * (qy + N * k)) * 3 + c] = y[qy];
+        for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
     }
     __syncthreads();
-    // z: interpolate along z -> values at the Gauss points; z-derivative
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int qx = r % N;
-        r /= N;
-        const int qy = r % N;
-        const int e = r / N;
+    // z: slot 1 -> values at the Gauss points (sV) and their z-derivative (slot 2)
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
         double x[N], y[N], dz[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) x[k] = sB[(e * N3 + qx + N * (qy + N * k)) * 3 + c];
+        for (int k = 0; k < N; ++k) x[k] = sG[base + 9 * N2 * k + 1];
         apply_eo<N, false>(T.S, x, y);
         apply_eo<N, true>(T.D, y, dz);
 #pragma unroll
         for (int qz = 0; qz < N; ++qz) {
-            const int q = qx + N * (qy + N * qz);
-            sA[(e * N3 + q) * 3 + c] = y[qz];
-            sG[((e * N3 + q) * 3 + c) * 3 + 2] = dz[qz];
+            sV[(base + 9 * N2 * qz) / 3] = y[qz];
+            sG[base + 9 * N2 * qz + 2] = dz[qz];
         }
     }
     __syncthreads();
-    // x- and y-derivatives of the values at the Gauss points
-    for (int t = tid; t < 2 * 3 * N2 * nE; t += NT) {
-        const int dir = t & 1;
-        int r = t >> 1;
-        const int c = r % 3;
-        r /= 3;
-        const int s = r % N;
-        r /= N;
-        const int qz = r % N;
-        const int e = r / N;
-        double x[N], y[N];
-        if (dir == 0) {  // line along x at (qy = s, qz)
+    // x- and y-derivatives of the values -> slots 0 and 1
 #pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sA[(e * N3 + l + N * (s + N * qz)) * 3 + c];
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        {   // x-line at (qy, qz) = (a, b)
+            const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
+            double x[N], y[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * l) / 3];
             apply_eo<N, true>(T.D, x, y);
 #pragma unroll
-            for (int qx = 0; qx < N; ++qx) sG[((e * N3 + qx + N * (s + N * qz)) * 3 + c) * 3 + 0] = y[qx];
-        } else {  // line along y at (qx = s, qz)
+            for (int qx = 0; qx < N; ++qx) sG[base + 9 * qx] = y[qx];
+        }
+        {   // y-line at (qx, qz) = (a, b)
+            const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
+            double x[N], y[N];
 #pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sA[(e * N3 + s + N * (l + N * qz)) * 3 + c];
+            for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * N * l) / 3];
             apply_eo<N, true>(T.D, x, y);
 #pragma unroll
-            for (int qy = 0; qy < N; ++qy) sG[((e * N3 + s + N * (qy + N * qz)) * 3 + c) * 3 + 1] = y[qy];
+            for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
         }
     }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Backward sweeps: on entry sG[((e*N3 + q)*3 + c)*3 + d] = Q[c][d] at q; adds
-// sum_q sum_d Q[c][d](q) dN_a/dxi_d (q) to dst at the cell's dofs.
+// Backward sweeps: on entry slot d of sG holds Q[c][d] at every point (made
+// visible by a barrier) and sBrick is zero.  Adds
+// sum_q sum_d Q[c][d](q) dN_a/dxi_d(q) of every cell to dst.  The cells'
+// contributions are summed in LDS; nodes inside the brick are then written
+// with plain stores, nodes on its faces (shared with neighbouring bricks)
+// with FP64 atomics.
 // ---------------------------------------------------------------------------
-template <int N, int NT>
-__device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const KParams& p, int cell0,
-                                                int nE, const Tables<N>& T, double* sA, double* sB,
-                                                const double* sG) {
-    constexpr int N2 = N * N, N3 = N2 * N, P = N - 1;
-    const int tid = threadIdx.x;
-    // transposed x- and y-derivatives
-    for (int t = tid; t < 2 * 3 * N2 * nE; t += NT) {
-        const int dir = t & 1;
-        int r = t >> 1;
-        const int c = r % 3;
-        r /= 3;
-        const int s = r % N;
-        r /= N;
-        const int qz = r % N;
-        const int e = r / N;
-        double x[N], y[N];
-        if (dir == 0) {
+template <int N>
+__device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const BrickPos& bp,
+                                                const BrickMap<N>& bm, const Tables<N>& T, double* sG,
+                                                double* sV, double* sBrick) {
+    using G = Geo<N>;
+    constexpr int N2 = G::N2, P = G::P;
+    // transposed x- and y-derivatives, in place in slots 0 and 1
 #pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sG[((e * N3 + l + N * (s + N * qz)) * 3 + c) * 3 + 0];
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        {
+            const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
+            double x[N], y[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * l];
             apply_eo<N, true>(T.Dt, x, y);
 #pragma unroll
-            for (int qx = 0; qx < N; ++qx) sA[(e * N3 + qx + N * (s + N * qz)) * 3 + c] = y[qx];
-        } else {
+            for (int qx = 0; qx < N; ++qx) sG[base + 9 * qx] = y[qx];
+        }
+        {
+            const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
+            double x[N], y[N];
 #pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sG[((e * N3 + s + N * (l + N * qz)) * 3 + c) * 3 + 1];
+            for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N * l + 1];
             apply_eo<N, true>(T.Dt, x, y);
 #pragma unroll
-            for (int qy = 0; qy < N; ++qy) sB[(e * N3 + s + N * (qy + N * qz)) * 3 + c] = y[qy];
+            for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
         }
     }
     __syncthreads();
-    // transposed z-derivative, sum of the three directions, transposed z-interpolation
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int qx = r % N;
-        r /= N;
-        const int qy = r % N;
-        const int e = r / N;
+    // transposed z-derivative, sum of the three directions, transposed
+    // z-interpolation -> sV at (qx, qy, k)
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
         double x[N], y[N], z[N];
 #pragma unroll
-        for (int l = 0; l < N; ++l) x[l] = sG[((e * N3 + qx + N * (qy + N * l)) * 3 + c) * 3 + 2];
+        for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N2 * l + 2];
         apply_eo<N, true>(T.Dt, x, y);
 #pragma unroll
-        for (int qz = 0; qz < N; ++qz) {
-            const int q = qx + N * (qy + N * qz);
-            y[qz] += sA[(e * N3 + q) * 3 + c] + sB[(e * N3 + q) * 3 + c];
-        }
+        for (int qz = 0; qz < N; ++qz) y[qz] += sG[base + 9 * N2 * qz] + sG[base + 9 * N2 * qz + 1];
         apply_eo<N, false>(T.St, y, z);
 #pragma unroll
-        for (int k = 0; k < N; ++k) sA[(e * N3 + qx + N * (qy + N * k)) * 3 + c] = z[k];
+        for (int k = 0; k < N; ++k) sV[(base + 9 * N2 * k) / 3] = z[k];
     }
     __syncthreads();
-    // transposed y-interpolation
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int qx = r % N;
-        r /= N;
-        const int k = r % N;
-        const int e = r / N;
+    // transposed y-interpolation: sV at (qx, qy, k) -> slot 0 at (qx, j, k)
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
         double x[N], y[N];
 #pragma unroll
-        for (int qy = 0; qy < N; ++qy) x[qy] = sA[(e * N3 + qx + N * (qy + N * k)) * 3 + c];
+        for (int qy = 0; qy < N; ++qy) x[qy] = sV[(base + 9 * N * qy) / 3];
         apply_eo<N, false>(T.St, x, y);
 #pragma unroll
-        for (int j = 0; j < N; ++j) sB[(e * N3 + qx + N * (j + N * k)) * 3 + c] = y[j];
+        for (int j = 0; j < N; ++j) sG[base + 9 * N * j] = y[j];
     }
     __syncthreads();
-    // transposed x-interpolation and scatter-add
-    for (int t = tid; t < 3 * N2 * nE; t += NT) {
-        const int c = t % 3;
-        int r = t / 3;
-        const int j = r % N;
-        r /= N;
-        const int k = r % N;
-        const int e = r / N;
+    // transposed x-interpolation, summed into the brick's nodes in LDS
+#pragma unroll
+    for (int it = 0; it < G::TPT; ++it) {
+        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
+        if (!L.valid) continue;
+        const int j = L.a, k = L.b;
+        const int base = gofs<N>(L.lc, N * (j + N * k), L.c);
         double x[N], y[N];
 #pragma unroll
-        for (int qx = 0; qx < N; ++qx) x[qx] = sB[(e * N3 + qx + N * (j + N * k)) * 3 + c];
+        for (int qx = 0; qx < N; ++qx) x[qx] = sG[base + 9 * qx];
         apply_eo<N, false>(T.St, x, y);
-        int ex, ey, ez;
-        cell_coords(p, cell0 + e, ex, ey, ez);
-        const int base = P * ex + p.Nx * ((P * ey + j) + p.Ny * (P * ez + k));
+        double* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            const int dof = 3 * (base + i) + c;
-            if (p.cmask != nullptr && p.cmask[dof]) continue;
-            unsafeAtomicAdd(dst + dof, y[i]);
-        }
+        for (int i = 0; i < N; ++i) atomicAdd(row + 3 * i, y[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < G::GPT; ++k) {
+        if (!(bm.exists >> k & 1u)) continue;
+        const double val = sBrick[threadIdx.x + k * G::NT];
+        if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
+        else dst[bm.dof[k]] = val;
     }
 }
 
 template <int N>
-__device__ __forceinline__ void load_grad(const double* sG, int e, int q, double g[3][3]) {
-    constexpr int N3 = N * N * N;
+__device__ __forceinline__ void load_slots(const double* sG, int tid, double g[3][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[c][d] = sG[((e * N3 + q) * 3 + c) * 3 + d];
+        for (int d = 0; d < 3; ++d) g[c][d] = sG[(tid * 3 + c) * 3 + d];
 }
 
 template <int N>
-__device__ __forceinline__ void store_grad(double* sG, int e, int q, const double g[3][3]) {
-    constexpr int N3 = N * N * N;
+__device__ __forceinline__ void store_slots(double* sG, int tid, const double g[3][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sG[((e * N3 + q) * 3 + c) * 3 + d] = g[c][d];
+        for (int d = 0; d < 3; ++d) sG[(tid * 3 + c) * 3 + d] = g[c][d];
 }
 
 __device__ __forceinline__ void inverse3(const double Jg[3][3], double Jinv[3][3], double& det) {
@@ -283,55 +394,68 @@ struct ModeInfo {
                                         MODE == MODE_RESIDUAL || MODE == MODE_STATE ||
                                         MODE == MODE_BUILD_GEOM || MODE == MODE_BUILD_T2 ||
                                         MODE == MODE_BUILD_T4;
+    static constexpr int cache_fields = MODE == MODE_APPLY_OTF_GEOM ? kGeomFields
+                                      : MODE == MODE_APPLY_T2       ? kT2Fields
+                                      : MODE == MODE_APPLY_T4       ? kT4Fields
+                                                                    : 0;
 };
 
 template <int N, int MODE>
-__global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const Tables<N> T) {
-    constexpr int E = Cfg<N>::E, NT = Cfg<N>::NT;
-    constexpr int N3 = N * N * N;
+__global__ __launch_bounds__(Geo<N>::NT) void cell_kernel(const KParams p, const Tables<N> T) {
+    using G = Geo<N>;
+    constexpr int N3 = G::N3;
     using MI = ModeInfo<MODE>;
-    __shared__ double sA[E * N3 * 3];
-    __shared__ double sB[E * N3 * 3];
-    __shared__ double sG[E * N3 * 9];
-    __shared__ double sEdge[E * 36];
+    __shared__ double sG[G::NQ * 9];
+    __shared__ double sV[G::NQ * 3];
+    __shared__ double sBrick[G::BRICK];
+    __shared__ double sEdge[G::CPB * 36];
 
-    const int nb = gridDim.x;
-    const int batch = xcd_batch(blockIdx.x, nb);
-    const int cell0 = batch * E;
-    const int nE = min(E, p.ne - cell0);
-    if (nE <= 0) return;  // uniform per block
+    const BrickPos bp = brick_pos(p, G::BX, G::BY, G::BZ, G::P);
+    const BrickMap<N> bm = brick_map<N>(p, bp);
     const int tid = threadIdx.x;
-    const int el = tid / N3;
-    const int q = tid - el * N3;
-    const bool active = el < nE;
-    const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
-    const int cell = cell0 + el;
-    const int64_t gq = (int64_t)cell * N3 + q;  // global quadrature index
+    // the quadrature point of this thread
+    const int lc = tid / N3;
+    const int q = tid - lc * N3;
+    const int lx = lc % G::BX, ly = (lc / G::BX) % G::BY, lz = lc / (G::BX * G::BY);
+    const bool active = lc < G::CPB && lx < bp.ncx && ly < bp.ncy && lz < bp.ncz;
+    const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
+    const int64_t gq = (int64_t)bp.brick * G::NQ + tid;   // brick-major cache index
+
+    // issue the global loads early: nodal values of the fields, per-point data
+    double ub[G::GPT], wb[G::GPT];
+    if constexpr (MI::fwd_u) brick_load<N>(p.u, bm, ub);
+    if constexpr (MI::fwd_w) brick_load<N>(p.w, bm, wb);
+    constexpr int NCF = MI::cache_fields > 0 ? MI::cache_fields : 1;
+    double cf[NCF];
+    if constexpr (MI::cache_fields > 0) {
+#pragma unroll
+        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? p.cache[f * p.nq_stride + gq] : 0.0;
+    }
 
     if constexpr (MI::vertex_geom) {
-        for (int t = tid; t < nE * 36; t += NT) {
-            const int e = t / 36;
-            const int r = t - 36 * e;
-            const int edge = r / 3, d = r - 3 * (r / 3);
-            int ex, ey, ez;
-            cell_coords(p, cell0 + e, ex, ey, ez);
-            // edge = 4*dir + a; endpoints differ in bit `dir`
+        // the 12 edge vectors of every cell's trilinear map
+        for (int t = tid; t < G::CPB * 36; t += G::NT) {
+            const int c = t / 36;
+            const int r = t - 36 * c;
+            const int cx = c % G::BX, cy = (c / G::BX) % G::BY, cz = c / (G::BX * G::BY);
+            if (cx >= bp.ncx || cy >= bp.ncy || cz >= bp.ncz) continue;
+            const int edge = r / 3, d = r - 3 * edge;
             const int dir = edge >> 2, a = edge & 3;
-            int v0;
-            if (dir == 0) v0 = 0 | ((a & 1) << 1) | ((a >> 1) << 2);
+            int v0;  // edge = 4*dir + a; its end points differ in bit `dir`
+            if (dir == 0) v0 = ((a & 1) << 1) | ((a >> 1) << 2);
             else if (dir == 1) v0 = (a & 1) | ((a >> 1) << 2);
             else v0 = (a & 1) | ((a >> 1) << 1);
             const int v1 = v0 | (1 << dir);
-            auto vid = [&](int v) {
-                return (ex + (v & 1)) + (p.nx + 1) * ((ey + ((v >> 1) & 1)) + (p.ny + 1) * (ez + (v >> 2)));
-            };
-            sEdge[e * 36 + r] = p.verts[3 * vid(v1) + d] - p.verts[3 * vid(v0) + d];
+            const int ex = bp.ex0 + cx, ey = bp.ey0 + cy, ez = bp.ez0 + cz;
+            const int vid0 = (ex + (v0 & 1)) + (p.nx + 1) * ((ey + ((v0 >> 1) & 1)) + (p.ny + 1) * (ez + (v0 >> 2)));
+            const int vid1 = (ex + (v1 & 1)) + (p.nx + 1) * ((ey + ((v1 >> 1) & 1)) + (p.ny + 1) * (ez + (v1 >> 2)));
+            sEdge[t] = p.verts[3 * vid1 + d] - p.verts[3 * vid0 + d];
         }
-        // made visible by the first barrier of the forward sweeps / below
     }
 
     double mu = p.mu, lam = p.lam;
     if (p.cell_mat != nullptr && active) {
+        const int cell = (bp.ex0 + lx) + p.nx * ((bp.ey0 + ly) + p.ny * (bp.ez0 + lz));
         mu = p.cell_mat[2 * cell];
         lam = p.cell_mat[2 * cell + 1];
     }
@@ -340,14 +464,14 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
         __syncthreads();
         if (active) {
             double Jg[3][3], Jinv[3][3], det;
-            jacobian_from_edges(sEdge + el * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
+            jacobian_from_edges(sEdge + lc * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
             inverse3(Jg, Jinv, det);
             const double JxW = det * T.qw[qx] * T.qw[qy] * T.qw[qz];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) p.cache_out[(3 * i + j) * p.nq_total + gq] = Jinv[i][j];
-            p.cache_out[9 * p.nq_total + gq] = JxW;
+                for (int j = 0; j < 3; ++j) p.cache_out[(3 * i + j) * p.nq_stride + gq] = Jinv[i][j];
+            p.cache_out[9 * p.nq_stride + gq] = JxW;
         }
         return;
     }
@@ -358,18 +482,20 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
     double F[3][3] = {};
     double du[3][3] = {};
     if constexpr (MI::fwd_u) {
-        forward_sweeps<N, NT, false>(p.u, p, cell0, nE, T, sA, sB, sG);
+        brick_store<N>(sBrick, ub);
+        __syncthreads();
+        forward_sweeps<N>(bp, T, sG, sV, sBrick, !MI::fwd_w);
         if (active) {
-            load_grad<N>(sG, el, q, du);
+            load_slots<N>(sG, tid, du);
             if constexpr (MODE == MODE_APPLY_OTF_GEOM) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) Jinv[i][j] = p.cache[(3 * i + j) * p.nq_total + gq];
-                JxW = p.cache[9 * p.nq_total + gq];
+                    for (int j = 0; j < 3; ++j) Jinv[i][j] = cf[3 * i + j];
+                JxW = cf[9];
             } else {
                 double Jg[3][3], det;
-                jacobian_from_edges(sEdge + el * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
+                jacobian_from_edges(sEdge + lc * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
                 inverse3(Jg, Jinv, det);
                 JxW = det * T.qw[qx] * T.qw[qy] * T.qw[qz];
             }
@@ -389,20 +515,20 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
             kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
             if constexpr (MODE == MODE_BUILD_T2) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[i * p.nq_total + gq] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) p.cache_out[i * p.nq_stride + gq] = M[i / 3][i % 3];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[(9 + i) * p.nq_total + gq] = tau[i];
-                p.cache_out[15 * p.nq_total + gq] = 2.0 * lam * JxW;
-                p.cache_out[16 * p.nq_total + gq] = 2.0 * (mu - 2.0 * lam * kin.lJ) * JxW;
+                for (int i = 0; i < 6; ++i) p.cache_out[(9 + i) * p.nq_stride + gq] = tau[i];
+                p.cache_out[15 * p.nq_stride + gq] = 2.0 * lam * JxW;
+                p.cache_out[16 * p.nq_stride + gq] = 2.0 * (mu - 2.0 * lam * kin.lJ) * JxW;
             } else {
                 double D21[21];
                 spatial_tangent_voigt(kin, mu, lam, JxW, D21);
 #pragma unroll
-                for (int i = 0; i < 21; ++i) p.cache_out[i * p.nq_total + gq] = D21[i];
+                for (int i = 0; i < 21; ++i) p.cache_out[i * p.nq_stride + gq] = D21[i];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[(21 + i) * p.nq_total + gq] = tau[i];
+                for (int i = 0; i < 6; ++i) p.cache_out[(21 + i) * p.nq_stride + gq] = tau[i];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[(27 + i) * p.nq_total + gq] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) p.cache_out[(27 + i) * p.nq_stride + gq] = M[i / 3][i % 3];
             }
         }
         return;
@@ -411,33 +537,26 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
     // ---------------- field w and the point-wise product
     double Q[3][3] = {};
     if constexpr (MI::fwd_w) {
-        if constexpr (!MI::fwd_u) __syncthreads();  // edge table (unused) / uniform entry
-        forward_sweeps<N, NT, true>(p.w, p, cell0, nE, T, sA, sB, sG);
+        // sBrick was last read before the forward sweeps' first barrier
+        brick_store<N>(sBrick, wb);
+        __syncthreads();
+        forward_sweeps<N>(bp, T, sG, sV, sBrick, true);
         if (active) {
             double dw[3][3];
-            load_grad<N>(sG, el, q, dw);
+            load_slots<N>(sG, tid, dw);
             if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM) {
                 pointwise_otf(dw, Jinv, kin, mu, lam, JxW, Q);
             } else if constexpr (MODE == MODE_APPLY_OTF_AD) {
                 pointwise_otf_ad(du, dw, Jinv, mu, lam, JxW, Q);
             } else if constexpr (MODE == MODE_APPLY_T2) {
-                double M[3][3], tau[6];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) M[i / 3][i % 3] = p.cache[i * p.nq_total + gq];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) tau[i] = p.cache[(9 + i) * p.nq_total + gq];
-                const double c1 = p.cache[15 * p.nq_total + gq];
-                const double c2 = p.cache[16 * p.nq_total + gq];
-                pointwise_t2(dw, M, tau, c1, c2, Q);
+                const double M[3][3] = {{cf[0], cf[1], cf[2]}, {cf[3], cf[4], cf[5]}, {cf[6], cf[7], cf[8]}};
+                const double tau[6] = {cf[9], cf[10], cf[11], cf[12], cf[13], cf[14]};
+                pointwise_t2(dw, M, tau, cf[15], cf[16], Q);
             } else if constexpr (MODE == MODE_APPLY_T4) {
-                double D21[21], tau[6], M[3][3];
-#pragma unroll
-                for (int i = 0; i < 21; ++i) D21[i] = p.cache[i * p.nq_total + gq];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) tau[i] = p.cache[(21 + i) * p.nq_total + gq];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) M[i / 3][i % 3] = p.cache[(27 + i) * p.nq_total + gq];
-                pointwise_t4(dw, M, D21, tau, Q);
+                const double M[3][3] = {{cf[27], cf[28], cf[29]}, {cf[30], cf[31], cf[32]},
+                                        {cf[33], cf[34], cf[35]}};
+                const double tau[6] = {cf[21], cf[22], cf[23], cf[24], cf[25], cf[26]};
+                pointwise_t4(dw, M, cf, tau, Q);
             }
         }
     } else if constexpr (MODE == MODE_RESIDUAL) {
@@ -445,10 +564,10 @@ __global__ __launch_bounds__(Cfg<N>::NT) void cell_kernel(const KParams p, const
     }
 
     if constexpr (MI::backward) {
-        // each thread overwrites only its own point's entries, which only it read
-        if (active) store_grad<N>(sG, el, q, Q);
+        // each thread overwrites only its own point's slots, which only it read
+        if (active) store_slots<N>(sG, tid, Q);
         __syncthreads();
-        backward_sweeps<N, NT>(p.v, p, cell0, nE, T, sA, sB, sG);
+        backward_sweeps<N>(p.v, bp, bm, T, sG, sV, sBrick);
     }
 }
 
@@ -500,9 +619,8 @@ static Tables<N> make_tables(const Tables1D& t) {
 
 template <int N, int MODE>
 static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream) {
-    constexpr int E = Cfg<N>::E, NT = Cfg<N>::NT;
-    const int nb = (p.ne + E - 1) / E;
-    hipLaunchKernelGGL((cell_kernel<N, MODE>), dim3(nb), dim3(NT), 0, stream, p, T);
+    const int nb = p.nbx * p.nby * p.nbz;
+    hipLaunchKernelGGL((cell_kernel<N, MODE>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T);
     return hipGetLastError();
 }
 
@@ -521,6 +639,19 @@ static hipError_t launch_n(int mode, const Tables1D& t, const KParams& p, hipStr
         case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2>(T, p, s);
         case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4>(T, p, s);
         default: return hipErrorInvalidValue;
+    }
+}
+
+void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick) {
+    switch (n) {
+#define MFE_BRICK_CASE(K)                                                        \
+    case K:                                                                      \
+        *bx = Geo<K>::BX; *by = Geo<K>::BY; *bz = Geo<K>::BZ; *points_per_brick = Geo<K>::NQ; \
+        return;
+        MFE_BRICK_CASE(2) MFE_BRICK_CASE(3) MFE_BRICK_CASE(4) MFE_BRICK_CASE(5) MFE_BRICK_CASE(6)
+        MFE_BRICK_CASE(7)
+#undef MFE_BRICK_CASE
+        default: *bx = *by = *bz = *points_per_brick = 0;
     }
 }
 

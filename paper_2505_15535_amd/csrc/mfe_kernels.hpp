@@ -30,7 +30,8 @@ struct KParams {
     int nx, ny, nz;            // cells per direction
     int ne;                    // nx*ny*nz
     int Nx, Ny;                // nodes per direction (x, y)
-    int64_t nq_total;          // ne * (p+1)^3, stride between cache fields
+    int nbx, nby, nbz;         // bricks per direction (one workgroup per brick)
+    int64_t nq_stride;         // bricks * points per brick: stride between cache fields
     const double* verts;       // (nx+1)(ny+1)(nz+1) x 3
     const double* u;           // state (gather source of the u field)
     const double* w;           // input vector (gather source of the w field)
@@ -39,7 +40,6 @@ struct KParams {
     double* cache_out;         // SoA cache written by BUILD modes
     const double* cell_mat;    // ne x (mu, lambda) or null
     double mu, lam;            // uniform material
-    const unsigned char* cmask;  // per-dof constraint mask or null
     int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
 };
 
@@ -53,6 +53,10 @@ struct Tables1D {
     double qp[8];
     double qw[8];
 };
+
+// Cells per brick in each direction and quadrature points per brick for
+// n = p+1 points per direction (zeros for an unsupported n).
+void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick);
 
 // Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream);
