@@ -400,8 +400,12 @@ struct ModeInfo {
                                                                     : 0;
 };
 
+#ifndef MFE_MIN_WAVES_PER_EU
+#define MFE_MIN_WAVES_PER_EU 1
+#endif
 template <int N, int MODE>
-__global__ __launch_bounds__(Geo<N>::NT) void cell_kernel(const KParams p, const Tables<N> T) {
+__global__ __launch_bounds__(Geo<N>::NT) __attribute__((amdgpu_waves_per_eu(MFE_MIN_WAVES_PER_EU)))
+void cell_kernel(const KParams p, const Tables<N> T) {
     using G = Geo<N>;
     constexpr int N3 = G::N3;
     using MI = ModeInfo<MODE>;
