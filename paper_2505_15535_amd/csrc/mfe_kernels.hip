@@ -423,7 +423,14 @@ void cell_kernel(const KParams p, const Tables<N> T) {
     const int lx = lc % G::BX, ly = (lc / G::BX) % G::BY, lz = lc / (G::BX * G::BY);
     const bool active = lc < G::CPB && lx < bp.ncx && ly < bp.ncy && lz < bp.ncz;
     const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
-    const int64_t gq = (int64_t)bp.brick * G::NQ + tid;   // brick-major cache index
+    // per-point caches are brick-major: the CF fields of a brick's points are one
+    // contiguous block, field f of this thread's point at cidx(f)
+    constexpr int CF = MODE == MODE_BUILD_GEOM ? kGeomFields
+                     : MODE == MODE_BUILD_T2   ? kT2Fields
+                     : MODE == MODE_BUILD_T4   ? kT4Fields
+                                               : (MI::cache_fields > 0 ? MI::cache_fields : 1);
+    const int64_t cbase = (int64_t)bp.brick * CF * G::NQ + tid;
+    auto cidx = [&](int f) { return cbase + (int64_t)f * G::NQ; };
 
     // issue the global loads early: nodal values of the fields, per-point data
     double ub[G::GPT], wb[G::GPT];
@@ -433,7 +440,7 @@ void cell_kernel(const KParams p, const Tables<N> T) {
     double cf[NCF];
     if constexpr (MI::cache_fields > 0) {
 #pragma unroll
-        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? p.cache[f * p.nq_stride + gq] : 0.0;
+        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? p.cache[cidx(f)] : 0.0;
     }
 
     if constexpr (MI::vertex_geom) {
@@ -474,8 +481,8 @@ void cell_kernel(const KParams p, const Tables<N> T) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) p.cache_out[(3 * i + j) * p.nq_stride + gq] = Jinv[i][j];
-            p.cache_out[9 * p.nq_stride + gq] = JxW;
+                for (int j = 0; j < 3; ++j) p.cache_out[cidx(3 * i + j)] = Jinv[i][j];
+            p.cache_out[cidx(9)] = JxW;
         }
         return;
     }
@@ -519,20 +526,20 @@ void cell_kernel(const KParams p, const Tables<N> T) {
             kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
             if constexpr (MODE == MODE_BUILD_T2) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[i * p.nq_stride + gq] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) p.cache_out[cidx(i)] = M[i / 3][i % 3];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[(9 + i) * p.nq_stride + gq] = tau[i];
-                p.cache_out[15 * p.nq_stride + gq] = 2.0 * lam * JxW;
-                p.cache_out[16 * p.nq_stride + gq] = 2.0 * (mu - 2.0 * lam * kin.lJ) * JxW;
+                for (int i = 0; i < 6; ++i) p.cache_out[cidx(9 + i)] = tau[i];
+                p.cache_out[cidx(15)] = 2.0 * lam * JxW;
+                p.cache_out[cidx(16)] = 2.0 * (mu - 2.0 * lam * kin.lJ) * JxW;
             } else {
                 double D21[21];
                 spatial_tangent_voigt(kin, mu, lam, JxW, D21);
 #pragma unroll
-                for (int i = 0; i < 21; ++i) p.cache_out[i * p.nq_stride + gq] = D21[i];
+                for (int i = 0; i < 21; ++i) p.cache_out[cidx(i)] = D21[i];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[(21 + i) * p.nq_stride + gq] = tau[i];
+                for (int i = 0; i < 6; ++i) p.cache_out[cidx(21 + i)] = tau[i];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[(27 + i) * p.nq_stride + gq] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) p.cache_out[cidx(27 + i)] = M[i / 3][i % 3];
             }
         }
         return;
