@@ -25,8 +25,9 @@
  *          must stay valid until the work queued on the given stream ends.
  *          The library never frees or retains them (set_state copies u).
  * Streams  every `stream` argument is a hipStream_t passed as void*; NULL
- *          means the null stream.  Work is queued on that stream and only
- *          mfe_set_state waits for it (once, to read the det F check).
+ *          means the null stream.  Work is queued on that stream; only
+ *          mfe_set_state (once, to read the det F check) and the solvers
+ *          (to read dot products) wait for it.
  * Errors   every call returns an mfe_status; nothing throws across the ABI.
  *          mfe_last_error() returns a message for the last failed call on
  *          that context (valid until the next call on it).
@@ -50,7 +51,7 @@ typedef enum mfe_status {
     MFE_ENOMEM = -3,        /* device allocation failed */
     MFE_EJACOBIAN = -4,     /* det F <= 0 or det J_g <= 0 at some quadrature point */
     MFE_ESTATE = -5,        /* apply before set_state, or cache older than the state */
-    MFE_ENOTCONV = -6,      /* reserved for the iterative solvers */
+    MFE_ENOTCONV = -6,      /* an iterative solver did not reach its tolerance */
     MFE_EUNSUPPORTED = -7   /* valid request that this build does not implement */
 } mfe_status;
 
@@ -136,7 +137,8 @@ int mfe_set_state(mfe_ctx* ctx, const double* u_dev, void* stream);
 
 /* Build the per-quadrature-point data of `strategy` from the current state
  * (Alg. 2 inputs): MFE_OTF_GEOM 10, MFE_T2 17, MFE_T4 36 doubles per point,
- * structure-of-arrays, owned by the context.  No-op for MFE_OTF and
+ * stored brick by brick (all fields of a brick's points contiguous), owned
+ * by the context.  No-op for MFE_OTF and
  * MFE_OTF_AD.  MFE_ESTATE without a state.  Asynchronous on `stream`. */
 int mfe_build_cache(mfe_ctx* ctx, int strategy, void* stream);
 
@@ -156,6 +158,73 @@ int mfe_apply_tangent(mfe_ctx* ctx, const void* w_dev, void* v_dev,
  * dofs.  u_dev, r_dev: device arrays of n_dofs doubles, must not overlap.
  * Does not change the state.  Asynchronous (det F is not checked). */
 int mfe_residual(mfe_ctx* ctx, const double* u_dev, double* r_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Newton-CG solver (Sec. 2.2-2.3): Newton's method on the weak form with the
+ * tangent applied matrix-free inside a (Jacobi-preconditioned) conjugate
+ * gradient method.  Dirichlet data live on the constrained dofs
+ * (mfe_set_constraints): the residual vanishes there, and a load step that
+ * moves the prescribed values is entered through the linearised response to
+ * the increment (first correction K_ff du_f = -R_f - K_fc dg, du_c = dg).
+ * ------------------------------------------------------------------------- */
+typedef enum mfe_preconditioner {
+    MFE_PC_NONE = 0,      /* plain CG */
+    MFE_PC_JACOBI = 1     /* inverse of the matrix-free diagonal of K(u) */
+} mfe_preconditioner;
+
+typedef struct mfe_solve_opts {
+    int strategy;         /* apply strategy used inside CG (mfe_strategy) */
+    int preconditioner;   /* mfe_preconditioner */
+    int max_newton;       /* Newton iterations allowed (>= 1) */
+    int max_cg;           /* CG iterations allowed per linear solve (>= 1) */
+    double newton_atol;   /* converged when ||R(u)||_2 <= newton_atol (free dofs) */
+    double cg_rtol;       /* CG stops when ||r||_2 <= cg_rtol * ||b||_2 */
+} mfe_solve_opts;
+
+#define MFE_HISTORY 64
+typedef struct mfe_solve_report {
+    int converged;             /* 1 if ||R|| <= newton_atol was reached */
+    int newton_iterations;     /* Newton corrections applied */
+    int cg_iterations;         /* CG iterations summed over the Newton steps */
+    int backtracks;            /* step halvings of the line search */
+    double initial_residual;   /* ||R(u_in)||_2 */
+    double final_residual;     /* ||R(u_out)||_2 */
+    double residual_history[MFE_HISTORY];  /* ||R|| before each correction, then the final one */
+} mfe_solve_report;
+
+/* Solve R(u) = 0 in place: u_dev (device, n_dofs doubles) holds the initial
+ * guess on entry and the last iterate on return.  g_dev (device, n_dofs
+ * doubles, or NULL) holds the new prescribed values at the constrained dofs
+ * (other entries are ignored); with NULL the constrained values of u are
+ * kept.  Each Newton step sets the state to u, builds the strategy's cache
+ * (and the second-order cache for the Jacobi diagonal), solves
+ * K(u) du = -R(u) by CG to cg_rtol, and updates u += a du, halving a (at
+ * most 12 times) until det F > 0 everywhere and ||R|| decreases; the first
+ * correction of a step with new Dirichlet values is applied in full.
+ * Synchronises the stream for every dot product.  Returns MFE_OK when
+ * converged, MFE_ENOTCONV when max_newton is exhausted or the line search
+ * fails, MFE_EJACOBIAN if the first correction inverts a cell; `report`
+ * (may be NULL) is filled in every case. */
+int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, const double* g_dev,
+                     mfe_solve_report* report, void* stream);
+
+/* x = K(u)^-1 b by (preconditioned) CG at the current state, starting from
+ * x = 0; b_dev, x_dev device arrays of n_dofs doubles (b must vanish at
+ * constrained dofs).  Uses opts->strategy, preconditioner, max_cg, cg_rtol.
+ * iterations_out / rel_residual_out (may be NULL) receive the iteration count
+ * and ||b - K x|| / ||b|| as tracked by CG.  MFE_ENOTCONV if max_cg is
+ * reached before cg_rtol.  Synchronises the stream. */
+int mfe_cg_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* b_dev, double* x_dev,
+                 int* iterations_out, double* rel_residual_out, void* stream);
+
+/* y = a x + b y on device arrays of n_dofs doubles (vector helper for load
+ * stepping drivers: predictors, copies with a = 1, b = 0).  Asynchronous. */
+int mfe_axpby(mfe_ctx* ctx, double a, const double* x_dev, double b, double* y_dev, void* stream);
+
+/* d = diagonal of K(u) at the current state (identity rows: 1 at
+ * constrained dofs), from the second-order cache, which this call builds if
+ * it is stale.  d_dev: device array of n_dofs doubles.  Asynchronous. */
+int mfe_diagonal(mfe_ctx* ctx, double* d_dev, void* stream);
 
 /* Average duration in milliseconds of the last `n` launches of the apply
  * kernel recorded with timing enabled, measured by HIP events recorded

@@ -28,6 +28,10 @@ MFE_OTF, MFE_OTF_GEOM, MFE_T2, MFE_T4, MFE_OTF_AD = 0, 1, 2, 3, 4
 STRATEGIES = {"otf": MFE_OTF, "otf_geom": MFE_OTF_GEOM, "t2": MFE_T2, "t4": MFE_T4, "otf_ad": MFE_OTF_AD}
 # sweep precisions
 MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
+# preconditioners of the Newton-CG solver
+MFE_PC_NONE, MFE_PC_JACOBI = 0, 1
+PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI}
+MFE_HISTORY = 64
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2505_15535_amd/build.py)")
@@ -39,6 +43,26 @@ import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+
+class SolveOpts(ctypes.Structure):
+    """struct mfe_solve_opts"""
+    _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
+                ("newton_atol", _d), ("cg_rtol", _d)]
+
+
+class SolveReport(ctypes.Structure):
+    """struct mfe_solve_report"""
+    _fields_ = [("converged", _i), ("newton_iterations", _i), ("cg_iterations", _i), ("backtracks", _i),
+                ("initial_residual", _d), ("final_residual", _d), ("residual_history", _d * MFE_HISTORY)]
+
+    def as_dict(self):
+        n = min(self.newton_iterations + 1, MFE_HISTORY)
+        return {"converged": bool(self.converged), "newton_iterations": self.newton_iterations,
+                "cg_iterations": self.cg_iterations, "backtracks": self.backtracks,
+                "initial_residual": self.initial_residual,
+                "final_residual": self.final_residual, "residual_history": list(self.residual_history[:n])}
+
 
 _SIGS = {
     "mfe_create": (_i, [ctypes.POINTER(_vp), _i]),
@@ -56,6 +80,10 @@ _SIGS = {
     "mfe_apply_tangent": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "mfe_residual": (_i, [_vp, _vp, _vp, _vp]),
     "mfe_set_timing": (_i, [_vp, _i]),
+    "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
+    "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
+    "mfe_diagonal": (_i, [_vp, _vp, _vp]),
+    "mfe_axpby": (_i, [_vp, _d, _vp, _d, _vp, _vp]),
     "mfe_apply_kernel_ms": (_d, [_vp, ctypes.POINTER(_i)]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -143,6 +171,34 @@ def mfe_apply_tangent(ctx, w_dev_ptr, v_dev_ptr, strategy, precision=MFE_FP64, s
 
 def mfe_residual(ctx, u_dev_ptr, r_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_residual(ctx, u_dev_ptr, r_dev_ptr, stream))
+
+
+def mfe_newton_solve(ctx, opts: SolveOpts, u_dev_ptr, g_dev_ptr=None, stream=None):
+    """Returns (status, SolveReport); raises MfeError unless the status is
+    MFE_OK or MFE_ENOTCONV (not converged within the iteration limits)."""
+    rep = SolveReport()
+    rc = _lib.mfe_newton_solve(ctx, ctypes.byref(opts), u_dev_ptr, g_dev_ptr, ctypes.byref(rep), stream)
+    if rc not in (MFE_OK, MFE_ENOTCONV):
+        raise MfeError(rc, mfe_last_error(ctx))
+    return rc, rep
+
+
+def mfe_cg_solve(ctx, opts: SolveOpts, b_dev_ptr, x_dev_ptr, stream=None):
+    """Returns (status, iterations, relative residual); raises MfeError unless
+    the status is MFE_OK or MFE_ENOTCONV."""
+    it, rel = _i(0), _d(0.0)
+    rc = _lib.mfe_cg_solve(ctx, ctypes.byref(opts), b_dev_ptr, x_dev_ptr, ctypes.byref(it), ctypes.byref(rel), stream)
+    if rc not in (MFE_OK, MFE_ENOTCONV):
+        raise MfeError(rc, mfe_last_error(ctx))
+    return rc, int(it.value), float(rel.value)
+
+
+def mfe_axpby(ctx, a, x_dev_ptr, b, y_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_axpby(ctx, float(a), x_dev_ptr, float(b), y_dev_ptr, stream))
+
+
+def mfe_diagonal(ctx, d_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_diagonal(ctx, d_dev_ptr, stream))
 
 
 def mfe_set_timing(ctx, enabled: bool):
@@ -243,6 +299,90 @@ class Operator:
         mfe_residual(self.ctx, _dev_f64(u, self.n_dofs, "u"), _dev_f64(out, self.n_dofs, "out"),
                      _stream_handle(stream))
         return out
+
+    @staticmethod
+    def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
+                   cg_rtol=1e-6):
+        return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
+                         int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol))
+
+    def newton_solve(self, u, g=None, stream=None, **opts):
+        """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the
+        constrained dofs.  Returns the report as a dict."""
+        gp = None if g is None else _dev_f64(g, self.n_dofs, "g")
+        rc, rep = mfe_newton_solve(self.ctx, self.solve_opts(**opts), _dev_f64(u, self.n_dofs, "u"), gp,
+                                   _stream_handle(stream))
+        out = rep.as_dict()
+        out["status"] = STATUS_NAMES.get(rc, rc)
+        return out
+
+    def cg_solve(self, b, x=None, stream=None, **opts):
+        """x = K(u)^-1 b at the current state; returns (x, iterations, relative residual, status)."""
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        rc, it, rel = mfe_cg_solve(self.ctx, self.solve_opts(**opts), _dev_f64(b, self.n_dofs, "b"),
+                                   _dev_f64(x, self.n_dofs, "x"), _stream_handle(stream))
+        return x, it, rel, STATUS_NAMES.get(rc, rc)
+
+    def diagonal(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
+        mfe_diagonal(self.ctx, _dev_f64(out, self.n_dofs, "out"), _stream_handle(stream))
+        return out
+
+    def axpby(self, a, x, b, y, stream=None):
+        """y = a x + b y (in place on y)."""
+        mfe_axpby(self.ctx, a, _dev_f64(x, self.n_dofs, "x"), b, _dev_f64(y, self.n_dofs, "y"),
+                  _stream_handle(stream))
+        return y
+
+    def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, **opts):
+        """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping).
+
+        boundary_values(t) -> (dofs, values): prescribed values at load t on the
+        constrained dofs.  Steps of 1/n_steps; a step whose Newton solve fails is
+        retried with half the increment (down to min_fraction) and the increment
+        grows again by 1.25x after each converged step (up to 1/n_steps); each
+        step starts from the linear extrapolation of the two previous converged
+        states.
+        u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
+        Returns a list of per-step reports (dicts with t, h and the solver report).
+        """
+        import numpy as np
+        import torch
+        n = self.n_dofs
+        prev = u.clone()
+        prev_h = None
+        g = torch.zeros(n, dtype=torch.float64, device=u.device)
+        t, h0 = 0.0, 1.0 / n_steps
+        h = h0
+        reports = []
+        while t < 1.0 - 1e-12:
+            h = min(h, 1.0 - t)
+            dofs, vals = boundary_values(t + h)
+            gh = np.zeros(n)
+            gh[np.asarray(dofs)] = vals
+            g.copy_(torch.from_numpy(gh))
+            trial = u.clone()
+            if prev_h is not None:  # trial = u + (h / prev_h) (u - prev)
+                self.axpby(1.0 + h / prev_h, u, 0.0, trial)
+                self.axpby(-h / prev_h, prev, 1.0, trial)
+            rep = self.newton_solve(trial, g=g, **opts)
+            if rep["converged"]:
+                prev.copy_(u)
+                u.copy_(trial)
+                prev_h = h
+                t += h
+                reports.append(dict(t=t, h=h, **rep))
+                h = min(h0, 1.25 * h)
+            else:
+                reports.append(dict(t=t + h, h=h, failed=True, **rep))
+                h *= 0.5
+                if h < min_fraction:
+                    raise MfeError(MFE_ENOTCONV, f"load step below {min_fraction} of the path at t = {t}")
+        return reports
 
     def set_timing(self, enabled=True):
         mfe_set_timing(self.ctx, enabled)

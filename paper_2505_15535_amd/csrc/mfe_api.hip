@@ -201,6 +201,12 @@ struct mfe_ctx {
     uint64_t cache_version[kNumCaches] = {0, 0, 0};
     bool cache_valid[kNumCaches] = {false, false, false};
     int* d_flag = nullptr;
+    // solver work space: 8 vectors (CG r, z, p, Kp, 1/diag; Newton R, du, dg),
+    // partial sums, pinned scalars, flag
+    double* d_work = nullptr;
+    double* d_partials = nullptr;
+    double* h_scalars = nullptr;
+    int* d_bad = nullptr;
     // timing of the apply kernel
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -232,6 +238,7 @@ void dfree(T*& p) {
 }
 
 void free_mesh_data(mfe_ctx* c) {
+    dfree(c->d_work);
     dfree(c->d_verts);
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
@@ -301,6 +308,10 @@ void mfe_destroy(mfe_ctx* c) {
     (void)hipDeviceSynchronize();
     free_mesh_data(c);
     dfree(c->d_flag);
+    dfree(c->d_work);
+    dfree(c->d_partials);
+    dfree(c->d_bad);
+    if (c->h_scalars) (void)hipHostFree(c->h_scalars);
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_stop) (void)hipEventDestroy(e);
     delete c;
@@ -491,7 +502,8 @@ int64_t mfe_cache_bytes(const mfe_ctx* c, int strategy) {
     return (int64_t)cache_fields(slot) * c->nq_stride * (int64_t)sizeof(double);
 }
 
-int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int precision, void* stream) {
+static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int precision, bool constrained,
+                      void* stream) {
     if (!c) return MFE_EINVAL;
     c->err.clear();
     if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
@@ -523,9 +535,9 @@ int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     p.w = static_cast<const double*>(w);
     p.v = static_cast<double*>(v);
     p.cache = slot >= 0 ? c->d_cache[slot] : nullptr;
-    if (c->n_con > 0) {  // the kernel reads w with the constrained entries zeroed
+    if (constrained && c->n_con > 0) {  // the kernel reads w with the constrained entries zeroed
         MFE_HIP(c, hipMemcpyAsync(c->d_wmask, w, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
-        MFE_HIP(c, mfe::launch_zero_indexed(c->d_cidx, c->n_con, c->d_wmask, s));
+        MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, c->d_wmask, s));
         p.w = c->d_wmask;
     }
     MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
@@ -545,9 +557,13 @@ int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
         c->ev_used++;
     }
-    if (c->n_con > 0)
+    if (constrained && c->n_con > 0)
         MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const double*>(w), p.v, s));
     return MFE_OK;
+}
+
+int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int precision, void* stream) {
+    return apply_impl(c, w, v, strategy, precision, true, stream);
 }
 
 int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
@@ -563,9 +579,280 @@ int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
     p.v = r;
     MFE_HIP(c, mfe::launch_fill(r, c->n_dofs, 0.0, s));
     MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_RESIDUAL, c->tab, p, s));
-    if (c->n_con > 0) MFE_HIP(c, mfe::launch_zero_indexed(c->d_cidx, c->n_con, r, s));
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, r, s));
     return MFE_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ solvers
+namespace {
+
+int ensure_work(mfe_ctx* c) {
+    if (!c->d_work) MFE_HIP(c, hipMalloc(&c->d_work, 8 * c->n_dofs * sizeof(double)));
+    if (!c->d_partials) MFE_HIP(c, hipMalloc(&c->d_partials, (2 * mfe::kDotBlocks + 2) * sizeof(double)));
+    if (!c->d_bad) MFE_HIP(c, hipMalloc(&c->d_bad, sizeof(int)));
+    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 4 * sizeof(double), hipHostMallocDefault));
+    return MFE_OK;
+}
+
+// two dot products (a.b, c.d) read back to the host
+int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const double* y, hipStream_t s,
+         double& ab, double& xy) {
+    double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    MFE_HIP(c, mfe::launch_dot2(a, b, x, y, c->n_dofs, c->d_partials, out, s));
+    MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipStreamSynchronize(s));
+    ab = c->h_scalars[0];
+    xy = c->h_scalars[1];
+    return MFE_OK;
+}
+
+int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
+    if (!o) return fail(c, MFE_EINVAL, "null options");
+    if (o->strategy < MFE_OTF || o->strategy > MFE_OTF_AD) return fail(c, MFE_EINVAL, "unknown strategy");
+    if (o->preconditioner != MFE_PC_NONE && o->preconditioner != MFE_PC_JACOBI)
+        return fail(c, MFE_EINVAL, "unknown preconditioner");
+    if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
+    if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
+    return MFE_OK;
+}
+
+// diagonal of K at the current state into d (identity rows at constrained dofs)
+int diagonal_into(mfe_ctx* c, double* d, hipStream_t s) {
+    if (!c->cache_valid[1] || c->cache_version[1] != c->state_version) {
+        const int rc = mfe_build_cache(c, MFE_T2, s);
+        if (rc != MFE_OK) return rc;
+    }
+    MFE_HIP(c, mfe::launch_fill(d, c->n_dofs, 0.0, s));
+    KParams p = base_params(c);
+    p.cache = c->d_cache[1];
+    MFE_HIP(c, mfe::launch_diagonal(c->tab, p, d, s));
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 1.0, d, s));  // identity rows
+    return MFE_OK;
+}
+
+// preconditioned CG on K(u) x = b, x starts at 0.  Work vectors: r, z, p, Ap, dinv.
+int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStream_t s, int& iters, double& rel) {
+    const int64_t n = c->n_dofs;
+    double* r = c->d_work + 0 * n;
+    double* z = c->d_work + 1 * n;
+    double* pv = c->d_work + 2 * n;
+    double* Ap = c->d_work + 3 * n;
+    double* dinv = c->d_work + 4 * n;
+    iters = 0;
+    rel = 0.0;
+    const bool jac = o->preconditioner == MFE_PC_JACOBI;
+    if (jac) {
+        int rc = diagonal_into(c, dinv, s);
+        if (rc != MFE_OK) return rc;
+        MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
+        MFE_HIP(c, mfe::launch_invert(dinv, n, c->d_bad, s));
+        int bad = 0;
+        MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        if (bad) return fail(c, MFE_EJACOBIAN, "tangent diagonal is not positive: no Jacobi preconditioner");
+    }
+    MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, b, r, n, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, jac ? dinv : nullptr, r, z, n, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
+    double rr, rz;
+    int rc = dot2(c, r, r, r, z, s, rr, rz);
+    if (rc != MFE_OK) return rc;
+    const double bnorm = std::sqrt(rr);
+    if (bnorm == 0.0) return MFE_OK;
+    double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    for (int it = 1; it <= o->max_cg; ++it) {
+        rc = mfe_apply_tangent(c, pv, Ap, o->strategy, MFE_FP64, s);
+        if (rc != MFE_OK) return rc;
+        double pAp, unused;
+        rc = dot2(c, pv, Ap, nullptr, nullptr, s, pAp, unused);
+        if (rc != MFE_OK) return rc;
+        if (!(pAp > 0.0)) return fail(c, MFE_ENOTCONV, "CG breakdown: p.Kp <= 0 (tangent not positive definite)");
+        const double alpha = rz / pAp;
+        MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, jac ? dinv : nullptr, alpha, n, c->d_partials, out, s));
+        MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        rr = c->h_scalars[0];
+        const double rz_new = c->h_scalars[1];
+        iters = it;
+        rel = std::sqrt(rr) / bnorm;
+        if (rel <= o->cg_rtol) return MFE_OK;
+        MFE_HIP(c, mfe::launch_axpby(1.0, z, rz_new / rz, pv, n, s));
+        rz = rz_new;
+    }
+    return fail(c, MFE_ENOTCONV, "CG did not reach its tolerance");
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfe_axpby(mfe_ctx* c, double a, const double* x, double b, double* y, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!x || !y) return fail(c, MFE_EINVAL, "null vector");
+    DeviceGuard g(c->device);
+    MFE_HIP(c, mfe::launch_axpby(a, x, b, y, c->n_dofs, static_cast<hipStream_t>(stream)));
+    return MFE_OK;
+}
+
+int mfe_diagonal(mfe_ctx* c, double* d, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    if (!d) return fail(c, MFE_EINVAL, "null vector");
+    DeviceGuard g(c->device);
+    int rc = ensure_work(c);
+    if (rc != MFE_OK) return rc;
+    return diagonal_into(c, d, static_cast<hipStream_t>(stream));
+}
+
+int mfe_cg_solve(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, int* iterations_out,
+                 double* rel_out, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    int rc = check_opts(c, o);
+    if (rc != MFE_OK) return rc;
+    if (!b || !x) return fail(c, MFE_EINVAL, "null vector");
+    if (overlaps(b, x, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "b and x overlap");
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = ensure_work(c);
+    if (rc != MFE_OK) return rc;
+    if (o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD) {
+        const int slot = cache_slot(o->strategy);
+        if (!c->cache_valid[slot] || (slot > 0 && c->cache_version[slot] != c->state_version)) {
+            rc = mfe_build_cache(c, o->strategy, s);
+            if (rc != MFE_OK) return rc;
+        }
+    }
+    int iters = 0;
+    double rel = 0.0;
+    rc = cg(c, o, b, x, s, iters, rel);
+    if (iterations_out) *iterations_out = iters;
+    if (rel_out) *rel_out = rel;
+    return rc;
+}
+
+int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const double* g, mfe_solve_report* rep,
+                     void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    mfe_solve_report local;
+    std::memset(&local, 0, sizeof(local));
+    if (rep) *rep = local;
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    int rc = check_opts(c, o);
+    if (rc != MFE_OK) return rc;
+    if (!u) return fail(c, MFE_EINVAL, "null vector");
+    DeviceGuard dg_guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = ensure_work(c);
+    if (rc != MFE_OK) return rc;
+    const int64_t n = c->n_dofs;
+    double* res = c->d_work + 5 * n;   // residual, then the right-hand side
+    double* du = c->d_work + 6 * n;    // Newton correction
+    double* dg = c->d_work + 7 * n;    // increment of the Dirichlet values
+    const bool has_dg = g != nullptr && c->n_con > 0;
+    if (has_dg) {
+        MFE_HIP(c, mfe::launch_fill(dg, n, 0.0, s));
+        MFE_HIP(c, mfe::launch_diff_indexed(c->d_cidx, c->n_con, g, u, dg, s));
+    }
+    const bool cached = o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD;
+    int status = MFE_ENOTCONV;
+    double rn = 0.0;
+    bool have_res = false;
+    for (int it = 0;; ++it) {
+        if (!have_res) {
+            rc = mfe_residual(c, u, res, s);
+            if (rc != MFE_OK) { status = rc; break; }
+            double rr, unused;
+            rc = dot2(c, res, res, nullptr, nullptr, s, rr, unused);
+            if (rc != MFE_OK) { status = rc; break; }
+            rn = std::sqrt(rr);
+        }
+        have_res = false;
+        if (it == 0) local.initial_residual = rn;
+        local.final_residual = rn;
+        if (it < MFE_HISTORY) local.residual_history[it] = rn;
+        if (!std::isfinite(rn)) { status = fail(c, MFE_ENOTCONV, "residual is not finite"); break; }
+        const bool first_step_of_load = it == 0 && has_dg;
+        if (!first_step_of_load && rn <= o->newton_atol) { local.converged = 1; status = MFE_OK; break; }
+        if (it == o->max_newton) { status = fail(c, MFE_ENOTCONV, "Newton did not converge"); break; }
+        rc = mfe_set_state(c, u, s);
+        if (rc != MFE_OK) { status = rc; break; }
+        if (cached) {
+            rc = mfe_build_cache(c, o->strategy, s);
+            if (rc != MFE_OK) { status = rc; break; }
+        }
+        MFE_HIP(c, mfe::launch_scale_mul(-1.0, nullptr, res, res, n, s));
+        if (first_step_of_load) {
+            // rhs_f = -R_f - (K dg)_f with the unconstrained operator, rhs_c = dg_c
+            rc = apply_impl(c, dg, du, o->strategy, MFE_FP64, false, s);
+            if (rc != MFE_OK) { status = rc; break; }
+            MFE_HIP(c, mfe::launch_axpby(-1.0, du, 1.0, res, n, s));
+            MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, dg, res, s));
+        }
+        int iters = 0;
+        double rel = 0.0;
+        rc = cg(c, o, res, du, s, iters, rel);
+        local.cg_iterations += iters;
+        if (rc != MFE_OK && rc != MFE_ENOTCONV) { status = rc; break; }
+        local.newton_iterations = it + 1;
+        if (first_step_of_load) {
+            MFE_HIP(c, mfe::launch_axpby(1.0, du, 1.0, u, n, s));
+            MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, g, u, s));  // exact Dirichlet values
+            continue;
+        }
+        // backtracking line search on ||R|| with det F > 0
+        double a = 1.0;
+        MFE_HIP(c, mfe::launch_axpby(1.0, du, 1.0, u, n, s));
+        bool accepted = false;
+        for (int k = 0; k <= 12; ++k) {
+            rc = mfe_set_state(c, u, s);
+            if (rc == MFE_OK) {
+                rc = mfe_residual(c, u, res, s);
+                if (rc != MFE_OK) break;
+                double rr, unused;
+                rc = dot2(c, res, res, nullptr, nullptr, s, rr, unused);
+                if (rc != MFE_OK) break;
+                const double rt = std::sqrt(rr);
+                if (rt < rn) {
+                    rn = rt;
+                    have_res = true;
+                    accepted = true;
+                    break;
+                }
+            } else if (rc != MFE_EJACOBIAN) {
+                break;
+            }
+            rc = MFE_OK;
+            if (k == 12) break;
+            a *= 0.5;  // u = u_old + a du
+            MFE_HIP(c, mfe::launch_axpby(-a, du, 1.0, u, n, s));
+            local.backtracks++;
+        }
+        if (rc != MFE_OK) { status = rc; break; }
+        if (!accepted) {
+            c->err.clear();
+            status = fail(c, MFE_ENOTCONV, "line search failed");
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    if (rep) *rep = local;
+    return status;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int mfe_set_timing(mfe_ctx* c, int enabled) {
     if (!c) return MFE_EINVAL;

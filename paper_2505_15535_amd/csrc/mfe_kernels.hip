@@ -583,6 +583,60 @@ void cell_kernel(const KParams p, const Tables<N> T) {
 }
 
 // ---------------------------------------------------------------------------
+// Diagonal of the tangent, for the Jacobi / Chebyshev smoothers of the
+// multigrid-preconditioned CG (Sec. 2.3), from the second-order cache in the
+// current configuration: with g = grad N_a = (dN_a/dxi) M,
+//   K_(a,i),(a,i) = sum_q [ c1 g_i^2 + c2 (|g|^2 + g_i^2) / 2 + g tau g ].
+// One thread per (cell, node) of a brick; contributions of all cells are
+// added with atomics.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(Geo<N>::NT) void diag_kernel(const KParams p, const DiagTables T,
+                                                          double* __restrict__ diag) {
+    using G = Geo<N>;
+    constexpr int N3 = G::N3, P = G::P;
+    __shared__ double sS[N * N], sSd[N * N];
+    const int tid = threadIdx.x;
+    if (tid < N * N) {
+        sS[tid] = T.S[tid / N][tid % N];
+        sSd[tid] = T.Sd[tid / N][tid % N];
+    }
+    __syncthreads();
+    const BrickPos bp = brick_pos(p, G::BX, G::BY, G::BZ, G::P);
+    const int lc = tid / N3;
+    const int a = tid - lc * N3;
+    const int lx = lc % G::BX, ly = (lc / G::BX) % G::BY, lz = lc / (G::BX * G::BY);
+    if (!(lc < G::CPB && lx < bp.ncx && ly < bp.ncy && lz < bp.ncz)) return;
+    const int i = a % N, j = (a / N) % N, k = a / G::N2;
+    const double* cache = p.cache + (int64_t)bp.brick * kT2Fields * G::NQ + lc * N3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < N3; ++q) {
+        const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
+        const double Si = sS[qx * N + i], Sj = sS[qy * N + j], Sk = sS[qz * N + k];
+        const double d0 = sSd[qx * N + i] * Sj * Sk;
+        const double d1 = Si * sSd[qy * N + j] * Sk;
+        const double d2 = Si * Sj * sSd[qz * N + k];
+        double M[9], t[6];
+#pragma unroll
+        for (int f = 0; f < 9; ++f) M[f] = cache[f * G::NQ + q];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) t[f] = cache[(9 + f) * G::NQ + q];
+        const double c1 = cache[15 * G::NQ + q], c2 = cache[16 * G::NQ + q];
+        double g[3];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) g[n] = fma(d0, M[n], fma(d1, M[3 + n], d2 * M[6 + n]));
+        const double gg = fma(g[0], g[0], fma(g[1], g[1], g[2] * g[2]));
+        const double gtg = t[0] * g[0] * g[0] + t[1] * g[1] * g[1] + t[2] * g[2] * g[2] +
+                           2.0 * (t[3] * g[1] * g[2] + t[4] * g[0] * g[2] + t[5] * g[0] * g[1]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += c1 * g[c] * g[c] + 0.5 * c2 * (gg + g[c] * g[c]) + gtg;
+    }
+    const int node = (P * (bp.ex0 + lx) + i) + p.Nx * ((P * (bp.ey0 + ly) + j) + p.Ny * (P * (bp.ez0 + lz) + k));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) unsafeAtomicAdd(diag + 3 * node + c, acc[c]);
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch
 // ---------------------------------------------------------------------------
 template <int N>
@@ -666,6 +720,34 @@ void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick) {
     }
 }
 
+template <int N>
+static hipError_t launch_diag_n(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream) {
+    DiagTables T;
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+            T.S[a][b] = t.S[a][b];
+            double s = 0.0;  // derivative of the nodal basis at the Gauss points: D S
+            for (int l = 0; l < t.n; ++l) s += t.D[a][l] * t.S[l][b];
+            T.Sd[a][b] = (a < t.n && b < t.n) ? s : 0.0;
+        }
+    const int nb = p.nbx * p.nby * p.nbz;
+    hipLaunchKernelGGL((diag_kernel<N>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream) {
+    if (p.ne <= 0) return hipSuccess;
+    switch (t.n) {
+        case 2: return launch_diag_n<2>(t, p, diag, stream);
+        case 3: return launch_diag_n<3>(t, p, diag, stream);
+        case 4: return launch_diag_n<4>(t, p, diag, stream);
+        case 5: return launch_diag_n<5>(t, p, diag, stream);
+        case 6: return launch_diag_n<6>(t, p, diag, stream);
+        case 7: return launch_diag_n<7>(t, p, diag, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream) {
     if (p.ne <= 0) return hipSuccess;
     switch (t.n) {
@@ -693,9 +775,24 @@ __global__ void copy_indexed_kernel(const int64_t* __restrict__ idx, int64_t n,
     if (i < n) dst[idx[i]] = src[idx[i]];
 }
 
-__global__ void zero_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, double* __restrict__ dst) {
+__global__ void set_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, double value,
+                                   double* __restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[idx[i]] = 0.0;
+    if (i < n) dst[idx[i]] = value;
+}
+
+__global__ void diff_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, const double* __restrict__ a,
+                                    const double* __restrict__ b, double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = a[idx[i]] - b[idx[i]];
+}
+
+hipError_t launch_diff_indexed(const int64_t* idx, int64_t n, const double* a, const double* b, double* dst,
+                               hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(diff_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n, a, b,
+                       dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream) {
@@ -714,10 +811,10 @@ hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src,
     return hipGetLastError();
 }
 
-hipError_t launch_zero_indexed(const int64_t* idx, int64_t n, double* dst, hipStream_t stream) {
+hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
-                       dst);
+    hipLaunchKernelGGL(set_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
+                       value, dst);
     return hipGetLastError();
 }
 

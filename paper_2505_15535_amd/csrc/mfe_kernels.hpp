@@ -61,9 +61,34 @@ void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick);
 // Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream);
 
+// Nodal basis values S and their derivatives Sd at the Gauss points.
+struct DiagTables {
+    double S[8][8];
+    double Sd[8][8];
+};
+
+// diag += diagonal of the tangent, from the second-order cache in p.cache
+// (which must be built for the current state).
+hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
+
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream);
+
+// Solver vector kernels.  Reductions use kDotBlocks partial sums (scratch of
+// 2*kDotBlocks doubles) and a fixed-order second pass, so they are
+// deterministic; `out` receives two doubles.
+constexpr int kDotBlocks = 1024;
+hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, int64_t n,
+                       double* partials, double* out, hipStream_t s);
+hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap, const double* dinv,
+                            double alpha, int64_t n, double* partials, double* out, hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s);
 hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
                                hipStream_t stream);
-hipError_t launch_zero_indexed(const int64_t* idx, int64_t n, double* dst, hipStream_t stream);
+// dst[idx[i]] = a[idx[i]] - b[idx[i]]
+hipError_t launch_diff_indexed(const int64_t* idx, int64_t n, const double* a, const double* b, double* dst,
+                               hipStream_t stream);
+hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t stream);
 
 }  // namespace mfe

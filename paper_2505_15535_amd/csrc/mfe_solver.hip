@@ -1,0 +1,151 @@
+// Vector kernels of the Newton-CG solver (Sec. 2.2-2.3): fused CG updates
+// and deterministic two-pass FP64 dot products.
+
+#include <hip/hip_runtime.h>
+
+#include "mfe_kernels.hpp"
+
+namespace mfe {
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    // wavefront reduction, then across the 4 wavefronts of the block
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    return s;
+}
+
+// partials[b] = sum a*b, partials[nb + b] = sum c*d over block b's grid-stride range
+__global__ __launch_bounds__(kRedThreads) void dot2_partial_kernel(const double* __restrict__ a,
+                                                                   const double* __restrict__ b,
+                                                                   const double* __restrict__ c,
+                                                                   const double* __restrict__ d, int64_t n,
+                                                                   double* __restrict__ partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        s0 = fma(a[i], b[i], s0);
+        if (c) s1 = fma(c[i], d[i], s1);
+    }
+    const double t0 = block_sum(s0, sh);
+    const double t1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = t0;
+        partials[gridDim.x + blockIdx.x] = t1;
+    }
+}
+
+// out[0..1] = sums of the two partial arrays (fixed order: deterministic)
+__global__ __launch_bounds__(kRedThreads) void reduce2_kernel(const double* __restrict__ partials, int nb,
+                                                              double* __restrict__ out) {
+    __shared__ double sh[kRedThreads / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        s0 += partials[i];
+        s1 += partials[nb + i];
+    }
+    const double t0 = block_sum(s0, sh);
+    const double t1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        out[0] = t0;
+        out[1] = t1;
+    }
+}
+
+// x += alpha p; r -= alpha Ap; z = dinv .* r (z = r without dinv); partial (r.r, r.z)
+__global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                                double* __restrict__ z, const double* __restrict__ p,
+                                                                const double* __restrict__ Ap,
+                                                                const double* __restrict__ dinv, double alpha,
+                                                                int64_t n, double* __restrict__ partials) {
+    __shared__ double sh[kRedThreads / 64];
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, Ap[i], r[i]);
+        r[i] = ri;
+        const double zi = dinv ? dinv[i] * ri : ri;
+        z[i] = zi;
+        s0 = fma(ri, ri, s0);
+        s1 = fma(ri, zi, s1);
+    }
+    const double t0 = block_sum(s0, sh);
+    const double t1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = t0;
+        partials[gridDim.x + blockIdx.x] = t1;
+    }
+}
+
+// y = a x + b y
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = fma(a, x[i], b * y[i]);
+}
+
+// y = s * x (elementwise product with s, or copy when s is null) times scale
+__global__ void scale_mul_kernel(double scale, const double* __restrict__ s, const double* __restrict__ x,
+                                 double* __restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = scale * (s ? s[i] * x[i] : x[i]);
+}
+
+// d = 1 / d (entries that are not positive and finite are an error for Jacobi)
+__global__ void invert_kernel(double* __restrict__ d, int64_t n, int* __restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = d[i];
+        if (!(v > 0.0) || !(v < 1e300)) atomicOr(bad, 1);
+        d[i] = 1.0 / v;
+    }
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t b = (n + kRedThreads - 1) / kRedThreads;
+    return (unsigned)(b > kDotBlocks ? kDotBlocks : (b < 1 ? 1 : b));
+}
+
+hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, int64_t n,
+                       double* partials, double* out, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    hipLaunchKernelGGL(dot2_partial_kernel, dim3(nb), dim3(kRedThreads), 0, s, a, b, c, d, n, partials);
+    hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap, const double* dinv,
+                            double alpha, int64_t n, double* partials, double* out, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, s, x, r, z, p, Ap, dinv, alpha, n,
+                       partials);
+    hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, x, b, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(scale_mul_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, scale, sc, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(invert_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, d, n, bad);
+    return hipGetLastError();
+}
+
+}  // namespace mfe

@@ -14,6 +14,7 @@ from .generators import (
     sine_displacement,
     random_vectors,
     rng_for,
+    clamp_and_twist,
 )
 
 __all__ = [
@@ -25,4 +26,5 @@ __all__ = [
     "sine_displacement",
     "random_vectors",
     "rng_for",
+    "clamp_and_twist",
 ]

@@ -94,3 +94,31 @@ def random_vectors(n_dofs: int, count: int, rng: np.random.Generator) -> np.ndar
     """``count`` i.i.d. N(0,1) vectors of length ``n_dofs`` (float64, shape (count, n_dofs))."""
     return rng.standard_normal(size=(count, n_dofs))
 
+
+
+def clamp_and_twist(nx: int, ny: int, nz: int, degree: int, lengths, theta: float):
+    """Dirichlet data of the twisted beam: every dof of the nodes on the face
+    x = 0 is 0; the nodes on the face x = Lx are rotated by ``theta`` about the
+    beam axis through c = (Lx, Ly/2, Lz/2): u = R_x(theta) (X - c) - (X - c).
+
+    Node positions are those of the undistorted box with equispaced nodes
+    (degree <= 2, where Gauss-Lobatto and equispaced points coincide).
+    Returns (dofs int64, values float64), dofs sorted.
+    """
+    if degree > 2:
+        raise ValueError("twist data assumes equispaced nodes (degree <= 2)")
+    lx, ly, lz = (float(v) for v in lengths)
+    nnx, nny, nnz = degree * nx + 1, degree * ny + 1, degree * nz + 1
+    J, K = np.meshgrid(np.arange(nny), np.arange(nnz), indexing="ij")
+    J, K = J.ravel(), K.ravel()
+    left = 0 + nnx * (J + nny * K)
+    right = (nnx - 1) + nnx * (J + nny * K)
+    y = J * (ly / (nny - 1)) - 0.5 * ly
+    z = K * (lz / (nnz - 1)) - 0.5 * lz
+    c, s = np.cos(theta), np.sin(theta)
+    uy = (c * y - s * z) - y
+    uz = (s * y + c * z) - z
+    dofs = np.concatenate([3 * left[:, None] + np.arange(3), 3 * right[:, None] + np.arange(3)]).ravel()
+    vals = np.concatenate([np.zeros((left.size, 3)), np.stack([np.zeros_like(uy), uy, uz], axis=1)]).ravel()
+    order = np.argsort(dofs)
+    return dofs[order].astype(np.int64), vals[order]
