@@ -169,7 +169,13 @@ int mfe_residual(mfe_ctx* ctx, const double* u_dev, double* r_dev, void* stream)
  * ------------------------------------------------------------------------- */
 typedef enum mfe_preconditioner {
     MFE_PC_NONE = 0,      /* plain CG */
-    MFE_PC_JACOBI = 1     /* inverse of the matrix-free diagonal of K(u) */
+    MFE_PC_JACOBI = 1,    /* inverse of the matrix-free diagonal of K(u) */
+    MFE_PC_GMG = 2        /* one geometric multigrid V-cycle (Sec. 2.3): nested
+                             boxes, each coarser one halving the cell counts
+                             while all three are even; level operators K(u_l)
+                             at the nodal interpolant u_l of the state;
+                             Chebyshev-Jacobi pre- and post-smoothing;
+                             Chebyshev-Jacobi on the coarsest level */
 } mfe_preconditioner;
 
 typedef struct mfe_solve_opts {
@@ -179,6 +185,12 @@ typedef struct mfe_solve_opts {
     int max_cg;           /* CG iterations allowed per linear solve (>= 1) */
     double newton_atol;   /* converged when ||R(u)||_2 <= newton_atol (free dofs) */
     double cg_rtol;       /* CG stops when ||r||_2 <= cg_rtol * ||b||_2 */
+    int mg_levels;        /* GMG: most levels, the finest included (0: as many
+                             as the cell counts allow) */
+    int cheb_degree;      /* GMG: Chebyshev degree of pre- and post-smoothing (>= 1) */
+    double cheb_range;    /* GMG: lambda_max / lambda_min of the smoothed spectrum (> 1) */
+    int coarse_degree;    /* GMG: Chebyshev degree on the coarsest level (>= 1) */
+    double coarse_range;  /* GMG: lambda_max / lambda_min on the coarsest level (> 1) */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64
@@ -213,7 +225,15 @@ int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, co
  * constrained dofs).  Uses opts->strategy, preconditioner, max_cg, cg_rtol.
  * iterations_out / rel_residual_out (may be NULL) receive the iteration count
  * and ||b - K x|| / ||b|| as tracked by CG.  MFE_ENOTCONV if max_cg is
- * reached before cg_rtol.  Synchronises the stream. */
+ * reached before cg_rtol.  Synchronises the stream.
+ * With MFE_PC_GMG the hierarchy (one child context per coarser level, the
+ * 1D transfer matrices, 8 vectors per level) is built by the first such solve
+ * and kept until the mesh, material or constraints change; every solve then
+ * interpolates the state to the coarser levels, builds their caches and
+ * inverse diagonals, and estimates lambda_max(D^-1 K) per level from 24
+ * Lanczos steps (Jacobi-CG on a fixed random right-hand side); the smoothers
+ * use 1.2 times that estimate.  A coarse state with det F <= 0 gives
+ * MFE_EJACOBIAN. */
 int mfe_cg_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* b_dev, double* x_dev,
                  int* iterations_out, double* rel_residual_out, void* stream);
 

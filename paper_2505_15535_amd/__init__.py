@@ -29,8 +29,8 @@ STRATEGIES = {"otf": MFE_OTF, "otf_geom": MFE_OTF_GEOM, "t2": MFE_T2, "t4": MFE_
 # sweep precisions
 MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
 # preconditioners of the Newton-CG solver
-MFE_PC_NONE, MFE_PC_JACOBI = 0, 1
-PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI}
+MFE_PC_NONE, MFE_PC_JACOBI, MFE_PC_GMG = 0, 1, 2
+PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI, "gmg": MFE_PC_GMG}
 MFE_HISTORY = 64
 
 if not os.path.exists(LIB_PATH):
@@ -48,7 +48,8 @@ _vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_doub
 class SolveOpts(ctypes.Structure):
     """struct mfe_solve_opts"""
     _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
-                ("newton_atol", _d), ("cg_rtol", _d)]
+                ("newton_atol", _d), ("cg_rtol", _d), ("mg_levels", _i), ("cheb_degree", _i),
+                ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d)]
 
 
 class SolveReport(ctypes.Structure):
@@ -302,9 +303,11 @@ class Operator:
 
     @staticmethod
     def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
-                   cg_rtol=1e-6):
+                   cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=30,
+                   coarse_range=200.0):
         return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
-                         int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol))
+                         int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol), int(mg_levels),
+                         int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range))
 
     def newton_solve(self, u, g=None, stream=None, **opts):
         """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the
@@ -314,6 +317,8 @@ class Operator:
                                    _stream_handle(stream))
         out = rep.as_dict()
         out["status"] = STATUS_NAMES.get(rc, rc)
+        if rc != MFE_OK:
+            out["message"] = mfe_last_error(self.ctx)
         return out
 
     def cg_solve(self, b, x=None, stream=None, **opts):
@@ -383,6 +388,10 @@ class Operator:
                 if h < min_fraction:
                     raise MfeError(MFE_ENOTCONV, f"load step below {min_fraction} of the path at t = {t}")
         return reports
+
+    def last_error(self):
+        """Message of the last failed call on this operator ('' if none)."""
+        return mfe_last_error(self.ctx)
 
     def set_timing(self, enabled=True):
         mfe_set_timing(self.ctx, enabled)

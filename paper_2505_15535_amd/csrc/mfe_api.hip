@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -172,7 +173,31 @@ struct DeviceGuard {
     }
 };
 
+// 1D matrix in CSR form on the device
+struct DevCSR {
+    int rows = 0, cols = 0;
+    int* rowptr = nullptr;
+    int* col = nullptr;
+    double* val = nullptr;
+};
+
 }  // namespace
+
+// One level of the geometric multigrid hierarchy.  Level 0 is the context
+// itself; coarser levels own a child context.  Transfers to the next coarser
+// level are stored with the finer level.
+struct MGLevel {
+    mfe_ctx* ctx = nullptr;
+    bool own = false;
+    double* vec = nullptr;     // b, x, r, d, dinv, rnd, tmp1, tmp2 (n_dofs each)
+    double *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *dinv = nullptr, *rnd = nullptr;
+    double *tmp1 = nullptr, *tmp2 = nullptr;
+    double lmax = 0.0;         // estimate of the largest eigenvalue of D^-1 K
+    // per axis, between this level and the next coarser one: prolongation
+    // (fine x coarse), restriction (its transpose) and interpolation of the
+    // state to the coarse nodes (coarse x fine)
+    DevCSR P[3], R[3], I[3];
+};
 
 struct mfe_ctx {
     int device = 0;
@@ -207,6 +232,13 @@ struct mfe_ctx {
     double* d_partials = nullptr;
     double* h_scalars = nullptr;
     int* d_bad = nullptr;
+    // host copies used to derive coarser levels
+    std::vector<double> h_verts;
+    std::vector<double> h_cellmat;
+    std::vector<int64_t> h_cidx;
+    // geometric multigrid hierarchy (empty until the first GMG solve)
+    std::vector<MGLevel> mg;
+    int mg_request = -1;  // mg_levels the hierarchy was built for
     // timing of the apply kernel
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -237,7 +269,28 @@ void dfree(T*& p) {
     p = nullptr;
 }
 
+void free_csr(DevCSR& m) {
+    dfree(m.rowptr);
+    dfree(m.col);
+    dfree(m.val);
+    m.rows = m.cols = 0;
+}
+
+void mg_free(mfe_ctx* c) {
+    for (auto& L : c->mg) {
+        dfree(L.vec);
+        for (int a = 0; a < 3; ++a) {
+            free_csr(L.P[a]);
+            free_csr(L.R[a]);
+            free_csr(L.I[a]);
+        }
+        if (L.own && L.ctx) mfe_destroy(L.ctx);
+    }
+    c->mg.clear();
+}
+
 void free_mesh_data(mfe_ctx* c) {
+    mg_free(c);
     dfree(c->d_work);
     dfree(c->d_verts);
     dfree(c->d_cellmat);
@@ -378,6 +431,9 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
     const int64_t nv = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     MFE_HIP(c, hipMalloc(&c->d_verts, nv * 3 * sizeof(double)));
     MFE_HIP(c, hipMemcpy(c->d_verts, vxyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice));
+    c->h_verts.assign(vxyz, vxyz + nv * 3);
+    c->h_cellmat.clear();
+    c->h_cidx.clear();
     MFE_HIP(c, hipMalloc(&c->d_u, 3 * n_nodes * sizeof(double)));
     c->nx = nx;
     c->ny = ny;
@@ -415,7 +471,10 @@ int mfe_set_material(mfe_ctx* c, double mu, double lam, const double* per_cell) 
     DeviceGuard g(c->device);
     MFE_HIP(c, hipDeviceSynchronize());
     dfree(c->d_cellmat);
+    mg_free(c);
+    c->h_cellmat.clear();
     if (per_cell) {
+        c->h_cellmat.assign(per_cell, per_cell + 2 * c->ne);
         MFE_HIP(c, hipMalloc(&c->d_cellmat, c->ne * 2 * sizeof(double)));
         MFE_HIP(c, hipMemcpy(c->d_cellmat, per_cell, c->ne * 2 * sizeof(double), hipMemcpyHostToDevice));
     }
@@ -448,6 +507,8 @@ int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
         MFE_HIP(c, hipMemcpy(c->d_cidx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     }
     c->n_con = (int64_t)idx.size();
+    c->h_cidx = idx;
+    mg_free(c);
     return MFE_OK;
 }
 
@@ -596,11 +657,11 @@ int ensure_work(mfe_ctx* c) {
     return MFE_OK;
 }
 
-// two dot products (a.b, c.d) read back to the host
-int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const double* y, hipStream_t s,
+// two dot products (a.b, x.y) of length n read back to the host
+int dotn(mfe_ctx* c, int64_t n, const double* a, const double* b, const double* x, const double* y, hipStream_t s,
          double& ab, double& xy) {
     double* out = c->d_partials + 2 * mfe::kDotBlocks;
-    MFE_HIP(c, mfe::launch_dot2(a, b, x, y, c->n_dofs, c->d_partials, out, s));
+    MFE_HIP(c, mfe::launch_dot2(a, b, x, y, n, c->d_partials, out, s));
     MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     MFE_HIP(c, hipStreamSynchronize(s));
     ab = c->h_scalars[0];
@@ -608,11 +669,23 @@ int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const do
     return MFE_OK;
 }
 
+int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const double* y, hipStream_t s,
+         double& ab, double& xy) {
+    return dotn(c, c->n_dofs, a, b, x, y, s, ab, xy);
+}
+
 int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
     if (!o) return fail(c, MFE_EINVAL, "null options");
     if (o->strategy < MFE_OTF || o->strategy > MFE_OTF_AD) return fail(c, MFE_EINVAL, "unknown strategy");
-    if (o->preconditioner != MFE_PC_NONE && o->preconditioner != MFE_PC_JACOBI)
+    if (o->preconditioner < MFE_PC_NONE || o->preconditioner > MFE_PC_GMG)
         return fail(c, MFE_EINVAL, "unknown preconditioner");
+    if (o->preconditioner == MFE_PC_GMG) {
+        if (o->mg_levels < 0) return fail(c, MFE_EINVAL, "mg_levels must be >= 0");
+        if (o->cheb_degree < 1 || o->coarse_degree < 1) return fail(c, MFE_EINVAL, "Chebyshev degrees must be >= 1");
+        if (!(o->cheb_range > 1.0) || !(o->coarse_range > 1.0) || !std::isfinite(o->cheb_range) ||
+            !std::isfinite(o->coarse_range))
+            return fail(c, MFE_EINVAL, "Chebyshev ranges must be finite and > 1");
+    }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
     return MFE_OK;
@@ -632,6 +705,396 @@ int diagonal_into(mfe_ctx* c, double* d, hipStream_t s) {
     return MFE_OK;
 }
 
+// ---------------------------------------------------------- multigrid (Sec. 2.3)
+
+// Lagrange basis of the Gauss-Lobatto support points x[0..p] evaluated at t
+void lagrange_at(int p, const double* x, double t, double* l) {
+    for (int k = 0; k <= p; ++k) {
+        double v = 1.0;
+        for (int m = 0; m <= p; ++m)
+            if (m != k) v *= (t - x[m]) / (x[k] - x[m]);
+        l[k] = v;
+    }
+}
+
+// 1D interpolation between the nodes of two Q_p lines, one with twice the
+// cells of the other: row i holds the weights of the `from` nodes that give
+// the value at `to` node i (nodal interpolation in the logical coordinate).
+void line_interp(int p, int from_cells, int to_cells, std::vector<int>& rowptr, std::vector<int>& col,
+                 std::vector<double>& val) {
+    double x[8], l[8];
+    gll_points(p, x);
+    const int rows = p * to_cells + 1;
+    rowptr.assign(1, 0);
+    col.clear();
+    val.clear();
+    const double scale = (double)from_cells / to_cells;  // 2 or 1/2: exact
+    for (int i = 0; i < rows; ++i) {
+        const int ct = std::min(i / p, to_cells - 1);
+        const double pos = (ct + x[i - p * ct]) * scale;  // in units of `from` cells
+        const int cs = std::min((int)std::floor(pos), from_cells - 1);
+        lagrange_at(p, x, pos - cs, l);
+        for (int j = 0; j <= p; ++j) {
+            double w = l[j];
+            if (std::fabs(w) < 1e-14) continue;
+            if (std::fabs(w - 1.0) < 1e-14) w = 1.0;
+            col.push_back(p * cs + j);
+            val.push_back(w);
+        }
+        rowptr.push_back((int)col.size());
+    }
+}
+
+int upload_csr(mfe_ctx* c, DevCSR& m, int rows, int cols, const std::vector<int>& rp, const std::vector<int>& ci,
+               const std::vector<double>& v) {
+    m.rows = rows;
+    m.cols = cols;
+    MFE_HIP(c, hipMalloc(&m.rowptr, rp.size() * sizeof(int)));
+    MFE_HIP(c, hipMalloc(&m.col, std::max<size_t>(ci.size(), 1) * sizeof(int)));
+    MFE_HIP(c, hipMalloc(&m.val, std::max<size_t>(v.size(), 1) * sizeof(double)));
+    MFE_HIP(c, hipMemcpy(m.rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!ci.empty()) {
+        MFE_HIP(c, hipMemcpy(m.col, ci.data(), ci.size() * sizeof(int), hipMemcpyHostToDevice));
+        MFE_HIP(c, hipMemcpy(m.val, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return MFE_OK;
+}
+
+// transpose of a CSR matrix with `cols` columns
+void csr_transpose(int cols, const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
+                   std::vector<int>& trp, std::vector<int>& tci, std::vector<double>& tv) {
+    const int rows = (int)rp.size() - 1;
+    trp.assign(cols + 1, 0);
+    for (int e : ci) trp[e + 1]++;
+    for (int j = 0; j < cols; ++j) trp[j + 1] += trp[j];
+    tci.assign(ci.size(), 0);
+    tv.assign(v.size(), 0.0);
+    std::vector<int> fill(trp.begin(), trp.end() - 1);
+    for (int i = 0; i < rows; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int k = fill[ci[e]]++;
+            tci[k] = i;
+            tv[k] = v[e];
+        }
+}
+
+int child_fail(mfe_ctx* c, mfe_ctx* child, int rc, const char* what) {
+    return fail(c, rc, std::string("multigrid level setup (") + what + "): " + (child ? child->err : ""));
+}
+
+// Nested hierarchy: every coarser level halves the cell counts of the finer
+// one (vertices of the coarse box are the even-indexed fine vertices), keeps
+// the degree, averages (mu, lambda) over the 8 children, and constrains a
+// coarse dof when every fine dof its value is interpolated from is constrained.
+int mg_build(mfe_ctx* c, int max_levels) {
+    if (!c->mg.empty() && c->mg_request == max_levels) return MFE_OK;
+    mg_free(c);
+    c->mg_request = max_levels;
+    const int p = c->degree;
+    std::vector<mfe_ctx*> ctxs{c};
+    for (;;) {
+        mfe_ctx* f = ctxs.back();
+        if (max_levels > 0 && (int)ctxs.size() >= max_levels) break;
+        if (f->nx % 2 || f->ny % 2 || f->nz % 2) break;
+        const int nx = f->nx / 2, ny = f->ny / 2, nz = f->nz / 2;
+        std::vector<double> verts((size_t)(nx + 1) * (ny + 1) * (nz + 1) * 3);
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i) {
+                    const int64_t cv = i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+                    const int64_t fv = 2 * i + (int64_t)(f->nx + 1) * (2 * j + (int64_t)(f->ny + 1) * 2 * k);
+                    for (int d = 0; d < 3; ++d) verts[3 * cv + d] = f->h_verts[3 * fv + d];
+                }
+        mfe_ctx* child = nullptr;
+        int rc = mfe_create(&child, c->device);
+        if (rc != MFE_OK) return fail(c, rc, "multigrid level setup: mfe_create failed");
+        MGLevel L;
+        L.ctx = child;
+        L.own = true;
+        c->mg.push_back(L);  // owned from here on: freed by mg_free on any error
+        rc = mfe_mesh_box(child, nx, ny, nz, p, verts.data());
+        if (rc != MFE_OK) return child_fail(c, child, rc, "mesh");
+        std::vector<double> mat;
+        if (!f->h_cellmat.empty()) {
+            mat.assign((size_t)2 * child->ne, 0.0);
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        const int64_t ce = i + (int64_t)nx * (j + (int64_t)ny * k);
+                        for (int s = 0; s < 8; ++s) {
+                            const int64_t fe = (2 * i + (s & 1)) +
+                                               (int64_t)f->nx * ((2 * j + ((s >> 1) & 1)) + (int64_t)f->ny * (2 * k + (s >> 2)));
+                            mat[2 * ce] += 0.125 * f->h_cellmat[2 * fe];
+                            mat[2 * ce + 1] += 0.125 * f->h_cellmat[2 * fe + 1];
+                        }
+                    }
+        }
+        rc = mfe_set_material(child, f->mu, f->lam, mat.empty() ? nullptr : mat.data());
+        if (rc != MFE_OK) return child_fail(c, child, rc, "material");
+        ctxs.push_back(child);
+    }
+    // level 0 is the context itself
+    MGLevel top;
+    top.ctx = c;
+    top.own = false;
+    c->mg.insert(c->mg.begin(), top);
+    std::mt19937_64 gen(12345);
+    std::uniform_real_distribution<double> uni(-1.0, 1.0);
+    for (size_t l = 0; l < c->mg.size(); ++l) {
+        MGLevel& L = c->mg[l];
+        mfe_ctx* f = L.ctx;
+        const int64_t n = f->n_dofs;
+        MFE_HIP(c, hipMalloc(&L.vec, 8 * n * sizeof(double)));
+        L.b = L.vec;
+        L.x = L.vec + n;
+        L.r = L.vec + 2 * n;
+        L.d = L.vec + 3 * n;
+        L.dinv = L.vec + 4 * n;
+        L.rnd = L.vec + 5 * n;
+        L.tmp1 = L.vec + 6 * n;
+        L.tmp2 = L.vec + 7 * n;
+        std::vector<double> rnd(n);
+        for (auto& v : rnd) v = uni(gen);
+        MFE_HIP(c, hipMemcpy(L.rnd, rnd.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        if (l + 1 == c->mg.size()) break;
+        mfe_ctx* co = c->mg[l + 1].ctx;
+        const int fc[3] = {f->nx, f->ny, f->nz}, cc[3] = {co->nx, co->ny, co->nz};
+        const int fn[3] = {f->Nx, f->Ny, f->Nz}, cn[3] = {co->Nx, co->Ny, co->Nz};
+        std::vector<std::vector<int>> irp(3), ici(3);
+        std::vector<std::vector<double>> iv(3);
+        for (int a = 0; a < 3; ++a) {
+            std::vector<int> rp, ci, trp, tci;
+            std::vector<double> v, tv;
+            line_interp(p, cc[a], fc[a], rp, ci, v);  // coarse -> fine nodes
+            int rc = upload_csr(c, L.P[a], fn[a], cn[a], rp, ci, v);
+            if (rc != MFE_OK) return rc;
+            csr_transpose(cn[a], rp, ci, v, trp, tci, tv);
+            rc = upload_csr(c, L.R[a], cn[a], fn[a], trp, tci, tv);
+            if (rc != MFE_OK) return rc;
+            line_interp(p, fc[a], cc[a], irp[a], ici[a], iv[a]);  // fine -> coarse nodes
+            rc = upload_csr(c, L.I[a], cn[a], fn[a], irp[a], ici[a], iv[a]);
+            if (rc != MFE_OK) return rc;
+        }
+        // coarse constraints
+        std::vector<unsigned char> fmask(f->n_dofs, 0);
+        for (int64_t d : f->h_cidx) fmask[d] = 1;
+        std::vector<int64_t> ccon;
+        for (int k = 0; k < cn[2]; ++k)
+            for (int j = 0; j < cn[1]; ++j)
+                for (int i = 0; i < cn[0]; ++i)
+                    for (int comp = 0; comp < 3; ++comp) {
+                        bool all = true;
+                        for (int ez = irp[2][k]; all && ez < irp[2][k + 1]; ++ez)
+                            for (int ey = irp[1][j]; all && ey < irp[1][j + 1]; ++ey)
+                                for (int ex = irp[0][i]; all && ex < irp[0][i + 1]; ++ex) {
+                                    const int64_t fnode = ici[0][ex] + (int64_t)fn[0] * (ici[1][ey] + (int64_t)fn[1] * ici[2][ez]);
+                                    all = fmask[3 * fnode + comp] != 0;
+                                }
+                        if (all) ccon.push_back(3 * (i + (int64_t)cn[0] * (j + (int64_t)cn[1] * k)) + comp);
+                    }
+        const int rc = mfe_set_constraints(co, (int64_t)ccon.size(), ccon.data());
+        if (rc != MFE_OK) return child_fail(c, co, rc, "constraints");
+    }
+    return MFE_OK;
+}
+
+// out = M_z M_y M_x in for per-axis matrices M (out nodes m[], in nodes n[]),
+// through the two scratch arrays t1, t2 (each at least m_x n_y n_z, m_x m_y n_z)
+int tensor_apply(mfe_ctx* c, const DevCSR* M, const double* in, double* t1, double* t2, double* out, hipStream_t s) {
+    const int mx = M[0].rows, my = M[1].rows, mz = M[2].rows;
+    const int nx = M[0].cols, ny = M[1].cols, nz = M[2].cols;
+    MFE_HIP(c, mfe::launch_axis_csr(M[0].rowptr, M[0].col, M[0].val, 0, mx, ny, nz, nx, ny, in, t1, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[1].rowptr, M[1].col, M[1].val, 1, mx, my, nz, mx, ny, t1, t2, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[2].rowptr, M[2].col, M[2].val, 2, mx, my, mz, mx, my, t2, out, s));
+    return MFE_OK;
+}
+
+int level_apply(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* w, double* v, hipStream_t s) {
+    const int rc = mfe_apply_tangent(L.ctx, w, v, o->strategy, MFE_FP64, s);
+    if (rc != MFE_OK && L.ctx != c) return child_fail(c, L.ctx, rc, "apply");
+    return rc;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (a, b) by bisection
+// on the Sturm sequence count.
+double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) {
+    const int m = (int)a.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    // count of eigenvalues < x
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * std::max(1.0, std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) >= m) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
+// Estimate of lambda_max(D^-1 K) on a level: m steps of Jacobi-preconditioned
+// CG from the level's fixed random right-hand side; the CG coefficients give
+// the Lanczos tridiagonal matrix of D^-1 K, whose largest eigenvalue
+// approaches lambda_max from below.
+int lanczos_lmax(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, hipStream_t s, double& lmax) {
+    const int64_t n = L.ctx->n_dofs;
+    const int m = (int)std::min<int64_t>(24, n);
+    double* x = L.x;
+    double* r = L.b;
+    double* z = L.tmp1;
+    double* pv = L.d;
+    double* Ap = L.r;
+    double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, r, n, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, L.dinv, r, z, n, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
+    double rr, rz;
+    int rc = dotn(c, n, r, r, r, z, s, rr, rz);
+    if (rc != MFE_OK) return rc;
+    std::vector<double> diag, off;
+    double alpha_prev = 0.0, beta_prev = 0.0;
+    for (int k = 0; k < m; ++k) {
+        rc = level_apply(c, o, L, pv, Ap, s);
+        if (rc != MFE_OK) return rc;
+        double pAp, unused;
+        rc = dotn(c, n, pv, Ap, nullptr, nullptr, s, pAp, unused);
+        if (rc != MFE_OK) return rc;
+        if (!(pAp > 0.0) || !std::isfinite(pAp))
+            return fail(c, MFE_ENOTCONV, "eigenvalue estimate: level tangent is not positive definite");
+        const double alpha = rz / pAp;
+        diag.push_back(1.0 / alpha + (k > 0 ? beta_prev / alpha_prev : 0.0));
+        MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, L.dinv, alpha, n, c->d_partials, out, s));
+        MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        const double rz_new = c->h_scalars[1];
+        if (!(rz_new > 1e-30 * rz)) break;  // invariant subspace found
+        const double beta = rz_new / rz;
+        if (k + 1 < m) off.push_back(std::sqrt(beta) / alpha);
+        MFE_HIP(c, mfe::launch_axpby(1.0, z, beta, pv, n, s));
+        rz = rz_new;
+        alpha_prev = alpha;
+        beta_prev = beta;
+    }
+    off.resize(diag.size() > 0 ? diag.size() - 1 : 0);
+    lmax = tridiag_lmax(diag, off);
+    if (!(lmax > 0.0) || !std::isfinite(lmax)) return fail(c, MFE_ENOTCONV, "eigenvalue estimate failed");
+    return MFE_OK;
+}
+
+// Per linearisation point: interpolate the state to every coarser level,
+// build the level caches, the inverse diagonals and an estimate of the
+// largest eigenvalue of D^-1 K (Lanczos, through Jacobi-CG iterations from a
+// fixed random right-hand side).
+int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
+    const bool cached = o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD;
+    for (size_t l = 0; l < c->mg.size(); ++l) {
+        MGLevel& L = c->mg[l];
+        mfe_ctx* lc = L.ctx;
+        int rc;
+        if (l > 0) {
+            MGLevel& F = c->mg[l - 1];
+            rc = tensor_apply(c, F.I, F.ctx->d_u, F.tmp1, F.tmp2, L.x, s);
+            if (rc != MFE_OK) return rc;
+            rc = mfe_set_state(lc, L.x, s);
+            if (rc != MFE_OK) return child_fail(c, lc, rc, "state");
+        }
+        if (cached && (l > 0 || !lc->cache_valid[cache_slot(o->strategy)] ||
+                       lc->cache_version[cache_slot(o->strategy)] != lc->state_version)) {
+            rc = mfe_build_cache(lc, o->strategy, s);
+            if (rc != MFE_OK) return l ? child_fail(c, lc, rc, "cache") : rc;
+        }
+        rc = diagonal_into(lc, L.dinv, s);
+        if (rc != MFE_OK) return l ? child_fail(c, lc, rc, "diagonal") : rc;
+        MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
+        MFE_HIP(c, mfe::launch_invert(L.dinv, lc->n_dofs, c->d_bad, s));
+        int bad = 0;
+        MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        if (bad) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
+        double lam = 0.0;
+        rc = lanczos_lmax(c, o, L, s, lam);
+        if (rc != MFE_OK) return rc;
+        L.lmax = lam;
+    }
+    return MFE_OK;
+}
+
+// x = x + p(D^-1 K) D^-1 (b - K x): `degree` Chebyshev-Jacobi steps on
+// [lmax / range, lmax] with lmax 1.2 times the estimate (x = 0 on entry when
+// zero_start, which saves one operator application).
+int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* b, double* x, int degree, double range,
+              bool zero_start, hipStream_t s) {
+    const int64_t n = L.ctx->n_dofs;
+    const double hi = 1.2 * L.lmax, lo = hi / range;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    int rc;
+    if (zero_start) {
+        MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
+        MFE_HIP(c, mfe::launch_cheb(L.d, x, b, L.dinv, 0.0, 1.0 / theta, n, s));
+    } else {
+        rc = level_apply(c, o, L, x, L.r, s);
+        if (rc != MFE_OK) return rc;
+        MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
+        MFE_HIP(c, mfe::launch_cheb(L.d, x, L.r, L.dinv, 0.0, 1.0 / theta, n, s));
+    }
+    for (int k = 1; k < degree; ++k) {
+        rc = level_apply(c, o, L, x, L.r, s);
+        if (rc != MFE_OK) return rc;
+        MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        MFE_HIP(c, mfe::launch_cheb(L.d, x, L.r, L.dinv, rho_new * rho, 2.0 * rho_new / delta, n, s));
+        rho = rho_new;
+    }
+    return MFE_OK;
+}
+
+// one V-cycle x = V_l b on level l (x need not be initialised)
+int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const double* b, double* x, hipStream_t s) {
+    MGLevel& L = c->mg[l];
+    mfe_ctx* lc = L.ctx;
+    if (l + 1 == c->mg.size()) return chebyshev(c, o, L, b, x, o->coarse_degree, o->coarse_range, true, s);
+    int rc = chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, true, s);
+    if (rc != MFE_OK) return rc;
+    const int64_t n = lc->n_dofs;
+    rc = level_apply(c, o, L, x, L.r, s);
+    if (rc != MFE_OK) return rc;
+    MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
+    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.r, s));
+    MGLevel& C = c->mg[l + 1];
+    rc = tensor_apply(c, L.R, L.r, L.tmp1, L.tmp2, C.b, s);
+    if (rc != MFE_OK) return rc;
+    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, 0.0, C.b, s));
+    rc = vcycle(c, o, l + 1, C.b, C.x, s);
+    if (rc != MFE_OK) return rc;
+    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, 0.0, C.x, s));
+    rc = tensor_apply(c, L.P, C.x, L.tmp1, L.tmp2, L.r, s);  // L.r <- prolongated correction
+    if (rc != MFE_OK) return rc;
+    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.r, s));
+    MFE_HIP(c, mfe::launch_axpby(1.0, L.r, 1.0, x, n, s));
+    return chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, false, s);
+}
+
+// z = V r with the GMG hierarchy of c, then r.z
+int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s, double& rz) {
+    int rc = vcycle(c, o, 0, r, z, s);
+    if (rc != MFE_OK) return rc;
+    double unused;
+    return dot2(c, r, z, nullptr, nullptr, s, rz, unused);
+}
+
 // preconditioned CG on K(u) x = b, x starts at 0.  Work vectors: r, z, p, Ap, dinv.
 int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStream_t s, int& iters, double& rel) {
     const int64_t n = c->n_dofs;
@@ -643,6 +1106,14 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     iters = 0;
     rel = 0.0;
     const bool jac = o->preconditioner == MFE_PC_JACOBI;
+    const bool gmg = o->preconditioner == MFE_PC_GMG;
+    int rc;
+    if (gmg) {
+        rc = mg_build(c, o->mg_levels);
+        if (rc != MFE_OK) return rc;
+        rc = mg_update(c, o, s);
+        if (rc != MFE_OK) return rc;
+    }
     if (jac) {
         int rc = diagonal_into(c, dinv, s);
         if (rc != MFE_OK) return rc;
@@ -655,10 +1126,15 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     }
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, b, r, n, s));
-    MFE_HIP(c, mfe::launch_scale_mul(1.0, jac ? dinv : nullptr, r, z, n, s));
+    if (gmg) {
+        rc = vcycle(c, o, 0, r, z, s);
+        if (rc != MFE_OK) return rc;
+    } else {
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, jac ? dinv : nullptr, r, z, n, s));
+    }
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
     double rr, rz;
-    int rc = dot2(c, r, r, r, z, s, rr, rz);
+    rc = dot2(c, r, r, r, z, s, rr, rz);
     if (rc != MFE_OK) return rc;
     const double bnorm = std::sqrt(rr);
     if (bnorm == 0.0) return MFE_OK;
@@ -675,10 +1151,15 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
         rr = c->h_scalars[0];
-        const double rz_new = c->h_scalars[1];
+        double rz_new = c->h_scalars[1];
         iters = it;
         rel = std::sqrt(rr) / bnorm;
         if (rel <= o->cg_rtol) return MFE_OK;
+        if (gmg) {
+            rc = gmg_precondition(c, o, r, z, s, rz_new);
+            if (rc != MFE_OK) return rc;
+            if (!(rz_new > 0.0)) return fail(c, MFE_ENOTCONV, "multigrid preconditioner is not positive definite");
+        }
         MFE_HIP(c, mfe::launch_axpby(1.0, z, rz_new / rz, pv, n, s));
         rz = rz_new;
     }

@@ -84,6 +84,16 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
 hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s);
+
+// Multigrid kernels.  out = M in with the 1D CSR matrix M acting along `axis`
+// of nodal arrays [nz][ny][nx][3] (out extents nx_out, ny_out, nz_out; in has
+// nx_in, ny_in and the out extents elsewhere).
+hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* vals, int axis, int nx_out,
+                           int ny_out, int nz_out, int nx_in, int ny_in, const double* in, double* out,
+                           hipStream_t s);
+// d = c1 d + c2 dinv .* r;  x += d  (d is not read when c1 = 0)
+hipError_t launch_cheb(double* d, double* x, const double* r, const double* dinv, double c1, double c2, int64_t n,
+                       hipStream_t s);
 hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
                                hipStream_t stream);
 // dst[idx[i]] = a[idx[i]] - b[idx[i]]
