@@ -78,8 +78,16 @@ typedef enum mfe_strategy {
     MFE_OTF_AD = 4
 } mfe_strategy;
 
-/* Arithmetic of the sum-factorization sweeps.  Only MFE_FP64 is implemented;
- * the others return MFE_EUNSUPPORTED. */
+/* Arithmetic of the tangent apply (the precision direction of the method's
+ * growth: the sweeps inside a preconditioner need not be FP64).
+ *   MFE_FP64     w, v double; everything FP64.
+ *   MFE_SF_FP32  w, v float; the sum-factorization sweeps of w and the test
+ *                contraction in FP32, FP32 atomics; T2/T4 applies read the
+ *                FP32 cache (mfe_build_cache_fp32: values computed in FP64 from
+ *                F, J, log J and rounded once, all products FP32); on-the-fly
+ *                strategies keep u, F, J, log J and the point-wise response in
+ *                FP64 and round the result to FP32 before the contraction.
+ *   MFE_SF_BF16, MFE_SF_BF16X3  not built: MFE_EUNSUPPORTED. */
 typedef enum mfe_precision {
     MFE_FP64 = 0,
     MFE_SF_FP32 = 1,
@@ -142,14 +150,22 @@ int mfe_set_state(mfe_ctx* ctx, const double* u_dev, void* stream);
  * MFE_OTF_AD.  MFE_ESTATE without a state.  Asynchronous on `stream`. */
 int mfe_build_cache(mfe_ctx* ctx, int strategy, void* stream);
 
+/* FP32 copy of the T2 (17 floats per point) or T4 (36) cache for
+ * MFE_SF_FP32 applies, computed in FP64 from the current state and rounded
+ * once; same layout as the FP64 cache.  MFE_OTF_GEOM: builds the FP64
+ * geometry cache (its FP32 applies read it); MFE_OTF, MFE_OTF_AD: no-op.
+ * MFE_ESTATE without a state.  Asynchronous on `stream`. */
+int mfe_build_cache_fp32(mfe_ctx* ctx, int strategy, void* stream);
+
 /* Bytes of device memory held for `strategy`'s cache (0 if not built). */
 int64_t mfe_cache_bytes(const mfe_ctx* ctx, int strategy);
 
 /* v = K(u) w with u the current state (Alg. 1 for MFE_OTF/MFE_OTF_GEOM/
  * MFE_OTF_AD, Alg. 2 for MFE_T2/MFE_T4).  w_dev, v_dev: device arrays of
- * n_dofs doubles; v is overwritten; w and v must not overlap (MFE_EINVAL).
- * precision must be MFE_FP64.  MFE_ESTATE before set_state or when the
- * strategy's cache was not built for the current state.  Asynchronous. */
+ * n_dofs doubles (MFE_FP64) or floats (MFE_SF_FP32); v is overwritten; w and
+ * v must not overlap (MFE_EINVAL).  MFE_ESTATE before set_state or when the
+ * strategy's cache (FP32 cache for MFE_SF_FP32 with T2/T4) was not built for
+ * the current state.  Asynchronous. */
 int mfe_apply_tangent(mfe_ctx* ctx, const void* w_dev, void* v_dev,
                       int strategy, int precision, void* stream);
 
@@ -159,17 +175,24 @@ int mfe_apply_tangent(mfe_ctx* ctx, const void* w_dev, void* v_dev,
  * Does not change the state.  Asynchronous (det F is not checked). */
 int mfe_residual(mfe_ctx* ctx, const double* u_dev, double* r_dev, void* stream);
 
+/* *energy_host = stored energy sum_cells sum_q JxW_q Psi(F_q) of the law of
+ * eq. hypref at displacement u (u_dev: device array of n_dofs doubles);
+ * per-brick partial sums in a fixed order, so the result is reproducible.
+ * Not finite if det F <= 0 somewhere.  Synchronises the stream. */
+int mfe_energy(mfe_ctx* ctx, const double* u_dev, double* energy_host, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Newton-CG solver (Sec. 2.2-2.3): Newton's method on the weak form with the
- * tangent applied matrix-free inside a (Jacobi-preconditioned) conjugate
- * gradient method.  Dirichlet data live on the constrained dofs
- * (mfe_set_constraints): the residual vanishes there, and a load step that
- * moves the prescribed values is entered through the linearised response to
- * the increment (first correction K_ff du_f = -R_f - K_fc dg, du_c = dg).
+ * tangent applied matrix-free inside a preconditioned (Jacobi or geometric
+ * multigrid) conjugate gradient method.  Dirichlet data live on the
+ * constrained dofs (mfe_set_constraints): the residual vanishes there, and a
+ * load step that moves the prescribed values is entered through the
+ * linearised response to the increment (K_ff du_f = -R_f - K_fc dg,
+ * du_c = dg).
  * ------------------------------------------------------------------------- */
 typedef enum mfe_preconditioner {
     MFE_PC_NONE = 0,      /* plain CG */
-    MFE_PC_JACOBI = 1,    /* inverse of the matrix-free diagonal of K(u) */
+    MFE_PC_JACOBI = 1,    /* inverse of |diagonal of K(u)| (matrix-free diagonal) */
     MFE_PC_GMG = 2        /* one geometric multigrid V-cycle (Sec. 2.3): nested
                              boxes, each coarser one halving the cell counts
                              while all three are even; level operators K(u_l)
@@ -191,6 +214,10 @@ typedef struct mfe_solve_opts {
     double cheb_range;    /* GMG: lambda_max / lambda_min of the smoothed spectrum (> 1) */
     int coarse_degree;    /* GMG: Chebyshev degree on the coarsest level (>= 1) */
     double coarse_range;  /* GMG: lambda_max / lambda_min on the coarsest level (> 1) */
+    int mg_precision;     /* GMG: MFE_FP64, or MFE_SF_FP32 for an FP32 V-cycle (FP32
+                             vectors, transfers, smoother and MFE_SF_FP32 level
+                             applies) inside the FP64 CG, whose residual, dot
+                             products and update stay FP64 (defect correction) */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64
@@ -198,7 +225,9 @@ typedef struct mfe_solve_report {
     int converged;             /* 1 if ||R|| <= newton_atol was reached */
     int newton_iterations;     /* Newton corrections applied */
     int cg_iterations;         /* CG iterations summed over the Newton steps */
-    int backtracks;            /* step halvings of the line search */
+    int backtracks;            /* step halvings (line search and boundary steps) */
+    int pc_fallbacks;          /* CG solves in which GMG was replaced by Jacobi
+                                  (a level tangent was not positive definite) */
     double initial_residual;   /* ||R(u_in)||_2 */
     double final_residual;     /* ||R(u_out)||_2 */
     double residual_history[MFE_HISTORY];  /* ||R|| before each correction, then the final one */
@@ -211,12 +240,16 @@ typedef struct mfe_solve_report {
  * kept.  Each Newton step sets the state to u, builds the strategy's cache
  * (and the second-order cache for the Jacobi diagonal), solves
  * K(u) du = -R(u) by CG to cg_rtol, and updates u += a du, halving a (at
- * most 12 times) until det F > 0 everywhere and ||R|| decreases; the first
- * correction of a step with new Dirichlet values is applied in full.
+ * most 12 times) until det F > 0 everywhere and either ||R|| decreases or
+ * the stored energy satisfies E(u + a du) <= E(u) + 1e-4 a R.du.  New
+ * Dirichlet values enter through the first correction, K du = -R with
+ * du_c = g_c - u_c, applied in full; the prescribed values are then copied
+ * exactly.
  * Synchronises the stream for every dot product.  Returns MFE_OK when
- * converged, MFE_ENOTCONV when max_newton is exhausted or the line search
- * fails, MFE_EJACOBIAN if the first correction inverts a cell; `report`
- * (may be NULL) is filled in every case. */
+ * converged, MFE_ENOTCONV when max_newton is exhausted, the line search
+ * fails or the residual is not finite (the first correction inverted a
+ * cell); `report` (may be NULL) is filled in every case.  CG solves that stop early (iteration limit, negative
+ * curvature: the iterate so far is used) do not end the Newton iteration. */
 int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, const double* g_dev,
                      mfe_solve_report* report, void* stream);
 

@@ -28,6 +28,7 @@ MFE_OTF, MFE_OTF_GEOM, MFE_T2, MFE_T4, MFE_OTF_AD = 0, 1, 2, 3, 4
 STRATEGIES = {"otf": MFE_OTF, "otf_geom": MFE_OTF_GEOM, "t2": MFE_T2, "t4": MFE_T4, "otf_ad": MFE_OTF_AD}
 # sweep precisions
 MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": MFE_FP64, "fp32": MFE_SF_FP32, "bf16": MFE_SF_BF16, "bf16x3": MFE_SF_BF16X3}
 # preconditioners of the Newton-CG solver
 MFE_PC_NONE, MFE_PC_JACOBI, MFE_PC_GMG = 0, 1, 2
 PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI, "gmg": MFE_PC_GMG}
@@ -49,18 +50,20 @@ class SolveOpts(ctypes.Structure):
     """struct mfe_solve_opts"""
     _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
                 ("newton_atol", _d), ("cg_rtol", _d), ("mg_levels", _i), ("cheb_degree", _i),
-                ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d)]
+                ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d), ("mg_precision", _i)]
 
 
 class SolveReport(ctypes.Structure):
     """struct mfe_solve_report"""
     _fields_ = [("converged", _i), ("newton_iterations", _i), ("cg_iterations", _i), ("backtracks", _i),
-                ("initial_residual", _d), ("final_residual", _d), ("residual_history", _d * MFE_HISTORY)]
+                ("pc_fallbacks", _i), ("initial_residual", _d), ("final_residual", _d),
+                ("residual_history", _d * MFE_HISTORY)]
 
     def as_dict(self):
         n = min(self.newton_iterations + 1, MFE_HISTORY)
         return {"converged": bool(self.converged), "newton_iterations": self.newton_iterations,
                 "cg_iterations": self.cg_iterations, "backtracks": self.backtracks,
+                "pc_fallbacks": self.pc_fallbacks,
                 "initial_residual": self.initial_residual,
                 "final_residual": self.final_residual, "residual_history": list(self.residual_history[:n])}
 
@@ -77,9 +80,11 @@ _SIGS = {
     "mfe_set_constraints": (_i, [_vp, _i64, _vp]),
     "mfe_set_state": (_i, [_vp, _vp, _vp]),
     "mfe_build_cache": (_i, [_vp, _i, _vp]),
+    "mfe_build_cache_fp32": (_i, [_vp, _i, _vp]),
     "mfe_cache_bytes": (_i64, [_vp, _i]),
     "mfe_apply_tangent": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "mfe_residual": (_i, [_vp, _vp, _vp, _vp]),
+    "mfe_energy": (_i, [_vp, _vp, ctypes.POINTER(_d), _vp]),
     "mfe_set_timing": (_i, [_vp, _i]),
     "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
     "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
@@ -162,6 +167,10 @@ def mfe_build_cache(ctx, strategy, stream=None):
     return _check(ctx, _lib.mfe_build_cache(ctx, int(strategy), stream))
 
 
+def mfe_build_cache_fp32(ctx, strategy, stream=None):
+    return _check(ctx, _lib.mfe_build_cache_fp32(ctx, int(strategy), stream))
+
+
 def mfe_cache_bytes(ctx, strategy) -> int:
     return int(_lib.mfe_cache_bytes(ctx, int(strategy)))
 
@@ -220,13 +229,18 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _dev_f64(t, n, name):
+def _dev_tensor(t, n, name, dtype):
     import torch
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
-        raise ValueError(f"{name} must be a contiguous float64 tensor of {n} entries")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} entries")
     return t.data_ptr()
+
+
+def _dev_f64(t, n, name):
+    import torch
+    return _dev_tensor(t, n, name, torch.float64)
 
 
 class Operator:
@@ -279,19 +293,35 @@ class Operator:
     def set_state(self, u, stream=None):
         mfe_set_state(self.ctx, _dev_f64(u, self.n_dofs, "u"), _stream_handle(stream))
 
-    def build_cache(self, strategy, stream=None):
-        mfe_build_cache(self.ctx, STRATEGIES.get(strategy, strategy), _stream_handle(stream))
+    def build_cache(self, strategy, stream=None, precision="fp64"):
+        """Per-point data of `strategy` for applies of `precision` ("fp64" or "fp32")."""
+        prec = PRECISIONS.get(precision, precision)
+        build = mfe_build_cache_fp32 if prec == MFE_SF_FP32 else mfe_build_cache
+        build(self.ctx, STRATEGIES.get(strategy, strategy), _stream_handle(stream))
 
     def cache_bytes(self, strategy):
         return mfe_cache_bytes(self.ctx, STRATEGIES.get(strategy, strategy))
 
     def apply(self, w, out=None, strategy="otf", precision=MFE_FP64, stream=None):
+        """out = K(u) w.  precision "fp64" (float64 tensors) or "fp32" (float32
+        tensors: FP32 sweeps, see mfe_precision)."""
         import torch
+        prec = PRECISIONS.get(precision, precision)
         if out is None:
             out = torch.empty_like(w)
-        mfe_apply_tangent(self.ctx, _dev_f64(w, self.n_dofs, "w"), _dev_f64(out, self.n_dofs, "out"),
-                          STRATEGIES.get(strategy, strategy), precision, _stream_handle(stream))
+        if prec == MFE_SF_FP32:
+            wp, op = _dev_tensor(w, self.n_dofs, "w", torch.float32), _dev_tensor(out, self.n_dofs, "out", torch.float32)
+        else:
+            wp, op = _dev_f64(w, self.n_dofs, "w"), _dev_f64(out, self.n_dofs, "out")
+        mfe_apply_tangent(self.ctx, wp, op, STRATEGIES.get(strategy, strategy), prec, _stream_handle(stream))
         return out
+
+    def energy(self, u, stream=None):
+        """Stored energy at displacement u (float64 device tensor)."""
+        e = _d()
+        _check(self.ctx, _lib.mfe_energy(self.ctx, _dev_f64(u, self.n_dofs, "u"), ctypes.byref(e),
+                                         _stream_handle(stream)))
+        return e.value
 
     def residual(self, u, out=None, stream=None):
         import torch
@@ -304,10 +334,11 @@ class Operator:
     @staticmethod
     def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
                    cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=30,
-                   coarse_range=200.0):
+                   coarse_range=200.0, mg_precision="fp64"):
         return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
                          int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol), int(mg_levels),
-                         int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range))
+                         int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range),
+                         PRECISIONS.get(mg_precision, mg_precision))
 
     def newton_solve(self, u, g=None, stream=None, **opts):
         """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the

@@ -11,6 +11,7 @@
 #include <new>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mfe.h"
@@ -173,12 +174,21 @@ struct DeviceGuard {
     }
 };
 
-// 1D matrix in CSR form on the device
+// 1D matrix in CSR form on the device (values in FP64 and FP32)
 struct DevCSR {
     int rows = 0, cols = 0;
     int* rowptr = nullptr;
     int* col = nullptr;
     double* val = nullptr;
+    float* valf = nullptr;
+    const double* vals(double*) const { return val; }
+    const float* vals(float*) const { return valf; }
+};
+
+// Work vectors of one level in one precision
+template <typename T>
+struct MGVec {
+    T *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *dinv = nullptr, *tmp1 = nullptr, *tmp2 = nullptr;
 };
 
 }  // namespace
@@ -189,14 +199,18 @@ struct DevCSR {
 struct MGLevel {
     mfe_ctx* ctx = nullptr;
     bool own = false;
-    double* vec = nullptr;     // b, x, r, d, dinv, rnd, tmp1, tmp2 (n_dofs each)
-    double *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *dinv = nullptr, *rnd = nullptr;
-    double *tmp1 = nullptr, *tmp2 = nullptr;
+    double* vec = nullptr;     // FP64: b, x, r, d, dinv, tmp1, tmp2, rnd (n_dofs each)
+    float* vec32 = nullptr;    // FP32: b, x, r, d, dinv, tmp1, tmp2 (allocated on first FP32 use)
+    MGVec<double> v64;
+    MGVec<float> v32;
+    double* rnd = nullptr;     // fixed random start of the eigenvalue estimate
     double lmax = 0.0;         // estimate of the largest eigenvalue of D^-1 K
     // per axis, between this level and the next coarser one: prolongation
     // (fine x coarse), restriction (its transpose) and interpolation of the
     // state to the coarse nodes (coarse x fine)
     DevCSR P[3], R[3], I[3];
+    MGVec<double>& vecs(double*) { return v64; }
+    MGVec<float>& vecs(float*) { return v32; }
 };
 
 struct mfe_ctx {
@@ -225,10 +239,15 @@ struct mfe_ctx {
     double* d_cache[kNumCaches] = {nullptr, nullptr, nullptr};
     uint64_t cache_version[kNumCaches] = {0, 0, 0};
     bool cache_valid[kNumCaches] = {false, false, false};
+    // FP32 copies of the T2 and T4 caches (slots 1, 2) for mixed-precision applies
+    float* d_cache32[kNumCaches] = {nullptr, nullptr, nullptr};
+    uint64_t cache32_version[kNumCaches] = {0, 0, 0};
+    bool cache32_valid[kNumCaches] = {false, false, false};
     int* d_flag = nullptr;
     // solver work space: 8 vectors (CG r, z, p, Kp, 1/diag; Newton R, du, dg),
     // partial sums, pinned scalars, flag
     double* d_work = nullptr;
+    double* d_energy = nullptr;  // per-brick energy partials and their sum
     double* d_partials = nullptr;
     double* h_scalars = nullptr;
     int* d_bad = nullptr;
@@ -273,12 +292,14 @@ void free_csr(DevCSR& m) {
     dfree(m.rowptr);
     dfree(m.col);
     dfree(m.val);
+    dfree(m.valf);
     m.rows = m.cols = 0;
 }
 
 void mg_free(mfe_ctx* c) {
     for (auto& L : c->mg) {
         dfree(L.vec);
+        dfree(L.vec32);
         for (int a = 0; a < 3; ++a) {
             free_csr(L.P[a]);
             free_csr(L.R[a]);
@@ -292,6 +313,7 @@ void mg_free(mfe_ctx* c) {
 void free_mesh_data(mfe_ctx* c) {
     mg_free(c);
     dfree(c->d_work);
+    dfree(c->d_energy);
     dfree(c->d_verts);
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
@@ -299,7 +321,9 @@ void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_u);
     for (int i = 0; i < kNumCaches; ++i) {
         dfree(c->d_cache[i]);
+        dfree(c->d_cache32[i]);
         c->cache_valid[i] = false;
+        c->cache32_valid[i] = false;
     }
     c->n_con = 0;
     c->has_state = false;
@@ -481,6 +505,7 @@ int mfe_set_material(mfe_ctx* c, double mu, double lam, const double* per_cell) 
     c->mu = mu;
     c->lam = lam;
     c->cache_valid[1] = c->cache_valid[2] = false;  // material enters T2/T4
+    c->cache32_valid[1] = c->cache32_valid[2] = false;
     return MFE_OK;
 }
 
@@ -528,6 +553,7 @@ int mfe_set_state(mfe_ctx* c, const double* u, void* stream) {
     MFE_HIP(c, hipStreamSynchronize(s));
     c->state_version++;
     c->cache_valid[1] = c->cache_valid[2] = false;
+    c->cache32_valid[1] = c->cache32_valid[2] = false;
     if (flag) {
         c->has_state = false;
         return fail(c, MFE_EJACOBIAN, "det F <= 0 at some quadrature point");
@@ -556,6 +582,27 @@ int mfe_build_cache(mfe_ctx* c, int strategy, void* stream) {
     return MFE_OK;
 }
 
+int mfe_build_cache_fp32(mfe_ctx* c, int strategy, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    const int slot = cache_slot(strategy);
+    if (strategy == MFE_OTF || strategy == MFE_OTF_AD) return MFE_OK;
+    if (slot < 0) return fail(c, MFE_EINVAL, "unknown strategy");
+    if (slot == 0) return mfe_build_cache(c, strategy, stream);  // FP32 OTF_GEOM applies read FP64 geometry
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!c->d_cache32[slot])
+        MFE_HIP(c, hipMalloc(&c->d_cache32[slot], (size_t)cache_fields(slot) * c->nq_stride * sizeof(float)));
+    KParams p = base_params(c);
+    p.cache_out32 = c->d_cache32[slot];
+    MFE_HIP(c, mfe::launch_cell_kernel(slot == 1 ? mfe::MODE_BUILD_T2 : mfe::MODE_BUILD_T4, c->tab, p, s, true));
+    c->cache32_valid[slot] = true;
+    c->cache32_version[slot] = c->state_version;
+    return MFE_OK;
+}
+
 int64_t mfe_cache_bytes(const mfe_ctx* c, int strategy) {
     if (!c || !c->has_mesh) return 0;
     const int slot = cache_slot(strategy);
@@ -569,12 +616,14 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     c->err.clear();
     if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
     if (!w || !v) return fail(c, MFE_EINVAL, "null vector");
-    if (overlaps(w, v, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "w and v overlap");
-    if (precision != MFE_FP64) {
-        if (precision >= MFE_SF_FP32 && precision <= MFE_SF_BF16X3)
-            return fail(c, MFE_EUNSUPPORTED, "mixed-precision sweeps are not built");
+    if (precision != MFE_FP64 && precision != MFE_SF_FP32) {
+        if (precision >= MFE_SF_BF16 && precision <= MFE_SF_BF16X3)
+            return fail(c, MFE_EUNSUPPORTED, "BF16 sweeps are not built");
         return fail(c, MFE_EINVAL, "unknown precision");
     }
+    const bool fp32 = precision == MFE_SF_FP32;
+    const int64_t esize = fp32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
+    if (overlaps(w, v, c->n_dofs * esize)) return fail(c, MFE_EINVAL, "w and v overlap");
     int mode;
     switch (strategy) {
         case MFE_OTF: mode = mfe::MODE_APPLY_OTF; break;
@@ -586,22 +635,41 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     }
     if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
     const int slot = cache_slot(strategy);
-    if (slot >= 0) {
+    if (slot == 0 || (slot > 0 && !fp32)) {
         if (!c->cache_valid[slot] || (slot > 0 && c->cache_version[slot] != c->state_version))
             return fail(c, MFE_ESTATE, "cache not built for the current state");
+    } else if (slot > 0) {
+        if (!c->cache32_valid[slot] || c->cache32_version[slot] != c->state_version)
+            return fail(c, MFE_ESTATE, "FP32 cache not built for the current state");
     }
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     KParams p = base_params(c);
-    p.w = static_cast<const double*>(w);
-    p.v = static_cast<double*>(v);
-    p.cache = slot >= 0 ? c->d_cache[slot] : nullptr;
-    if (constrained && c->n_con > 0) {  // the kernel reads w with the constrained entries zeroed
-        MFE_HIP(c, hipMemcpyAsync(c->d_wmask, w, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
-        MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, c->d_wmask, s));
-        p.w = c->d_wmask;
+    if (slot >= 0) {
+        p.cache = c->d_cache[slot];
+        p.cache32 = c->d_cache32[slot];
     }
-    MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
+    const bool mask = constrained && c->n_con > 0;
+    if (fp32) {
+        p.w32 = static_cast<const float*>(w);
+        p.v32 = static_cast<float*>(v);
+        if (mask) {  // the kernel reads w with the constrained entries zeroed
+            float* wm = reinterpret_cast<float*>(c->d_wmask);
+            MFE_HIP(c, hipMemcpyAsync(wm, w, c->n_dofs * sizeof(float), hipMemcpyDeviceToDevice, s));
+            MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0f, wm, s));
+            p.w32 = wm;
+        }
+        MFE_HIP(c, mfe::launch_fill(p.v32, c->n_dofs, 0.0f, s));
+    } else {
+        p.w = static_cast<const double*>(w);
+        p.v = static_cast<double*>(v);
+        if (mask) {
+            MFE_HIP(c, hipMemcpyAsync(c->d_wmask, w, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+            MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, c->d_wmask, s));
+            p.w = c->d_wmask;
+        }
+        MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
+    }
     const bool timed = c->timing;
     if (timed) {
         if (c->ev_used == (int)c->ev_start.size()) {
@@ -613,18 +681,43 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         }
         MFE_HIP(c, hipEventRecord(c->ev_start[c->ev_used], s));
     }
-    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s));
+    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32));
     if (timed) {
         MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
         c->ev_used++;
     }
-    if (constrained && c->n_con > 0)
-        MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const double*>(w), p.v, s));
+    if (mask) {
+        if (fp32)
+            MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const float*>(w), p.v32, s));
+        else
+            MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const double*>(w), p.v, s));
+    }
     return MFE_OK;
 }
 
 int mfe_apply_tangent(mfe_ctx* c, const void* w, void* v, int strategy, int precision, void* stream) {
     return apply_impl(c, w, v, strategy, precision, true, stream);
+}
+
+int mfe_energy(mfe_ctx* c, const double* u, double* energy, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!u || !energy) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nb = (int64_t)c->nbx * c->nby * c->nbz;
+    if (!c->d_energy) MFE_HIP(c, hipMalloc(&c->d_energy, (nb + 1) * sizeof(double)));
+    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 4 * sizeof(double), hipHostMallocDefault));
+    KParams p = base_params(c);
+    p.u = u;
+    p.v = c->d_energy;
+    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_ENERGY, c->tab, p, s));
+    MFE_HIP(c, mfe::launch_sum(c->d_energy, nb, c->d_energy + nb, s));
+    MFE_HIP(c, hipMemcpyAsync(c->h_scalars + 3, c->d_energy + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipStreamSynchronize(s));
+    *energy = c->h_scalars[3];
+    return MFE_OK;
 }
 
 int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
@@ -685,6 +778,8 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
         if (!(o->cheb_range > 1.0) || !(o->coarse_range > 1.0) || !std::isfinite(o->cheb_range) ||
             !std::isfinite(o->coarse_range))
             return fail(c, MFE_EINVAL, "Chebyshev ranges must be finite and > 1");
+        if (o->mg_precision != MFE_FP64 && o->mg_precision != MFE_SF_FP32)
+            return fail(c, MFE_EINVAL, "mg_precision must be MFE_FP64 or MFE_SF_FP32");
     }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
@@ -752,10 +847,13 @@ int upload_csr(mfe_ctx* c, DevCSR& m, int rows, int cols, const std::vector<int>
     MFE_HIP(c, hipMalloc(&m.rowptr, rp.size() * sizeof(int)));
     MFE_HIP(c, hipMalloc(&m.col, std::max<size_t>(ci.size(), 1) * sizeof(int)));
     MFE_HIP(c, hipMalloc(&m.val, std::max<size_t>(v.size(), 1) * sizeof(double)));
+    MFE_HIP(c, hipMalloc(&m.valf, std::max<size_t>(v.size(), 1) * sizeof(float)));
     MFE_HIP(c, hipMemcpy(m.rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!ci.empty()) {
+        const std::vector<float> vf(v.begin(), v.end());
         MFE_HIP(c, hipMemcpy(m.col, ci.data(), ci.size() * sizeof(int), hipMemcpyHostToDevice));
         MFE_HIP(c, hipMemcpy(m.val, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        MFE_HIP(c, hipMemcpy(m.valf, vf.data(), vf.size() * sizeof(float), hipMemcpyHostToDevice));
     }
     return MFE_OK;
 }
@@ -845,14 +943,16 @@ int mg_build(mfe_ctx* c, int max_levels) {
         mfe_ctx* f = L.ctx;
         const int64_t n = f->n_dofs;
         MFE_HIP(c, hipMalloc(&L.vec, 8 * n * sizeof(double)));
-        L.b = L.vec;
-        L.x = L.vec + n;
-        L.r = L.vec + 2 * n;
-        L.d = L.vec + 3 * n;
-        L.dinv = L.vec + 4 * n;
-        L.rnd = L.vec + 5 * n;
-        L.tmp1 = L.vec + 6 * n;
-        L.tmp2 = L.vec + 7 * n;
+        double* const v[8] = {L.vec, L.vec + n, L.vec + 2 * n, L.vec + 3 * n,
+                              L.vec + 4 * n, L.vec + 5 * n, L.vec + 6 * n, L.vec + 7 * n};
+        L.v64.b = v[0];
+        L.v64.x = v[1];
+        L.v64.r = v[2];
+        L.v64.d = v[3];
+        L.v64.dinv = v[4];
+        L.v64.tmp1 = v[5];
+        L.v64.tmp2 = v[6];
+        L.rnd = v[7];
         std::vector<double> rnd(n);
         for (auto& v : rnd) v = uni(gen);
         MFE_HIP(c, hipMemcpy(L.rnd, rnd.data(), n * sizeof(double), hipMemcpyHostToDevice));
@@ -898,19 +998,47 @@ int mg_build(mfe_ctx* c, int max_levels) {
     return MFE_OK;
 }
 
-// out = M_z M_y M_x in for per-axis matrices M (out nodes m[], in nodes n[]),
-// through the two scratch arrays t1, t2 (each at least m_x n_y n_z, m_x m_y n_z)
-int tensor_apply(mfe_ctx* c, const DevCSR* M, const double* in, double* t1, double* t2, double* out, hipStream_t s) {
-    const int mx = M[0].rows, my = M[1].rows, mz = M[2].rows;
-    const int nx = M[0].cols, ny = M[1].cols, nz = M[2].cols;
-    MFE_HIP(c, mfe::launch_axis_csr(M[0].rowptr, M[0].col, M[0].val, 0, mx, ny, nz, nx, ny, in, t1, s));
-    MFE_HIP(c, mfe::launch_axis_csr(M[1].rowptr, M[1].col, M[1].val, 1, mx, my, nz, mx, ny, t1, t2, s));
-    MFE_HIP(c, mfe::launch_axis_csr(M[2].rowptr, M[2].col, M[2].val, 2, mx, my, mz, mx, my, t2, out, s));
+// FP32 work vectors of every level (first FP32 V-cycle)
+int ensure_mg32(mfe_ctx* c) {
+    for (auto& L : c->mg) {
+        if (L.vec32) continue;
+        const int64_t n = L.ctx->n_dofs;
+        MFE_HIP(c, hipMalloc(&L.vec32, 7 * n * sizeof(float)));
+        float* const v[7] = {L.vec32, L.vec32 + n, L.vec32 + 2 * n, L.vec32 + 3 * n,
+                             L.vec32 + 4 * n, L.vec32 + 5 * n, L.vec32 + 6 * n};
+        L.v32.b = v[0];
+        L.v32.x = v[1];
+        L.v32.r = v[2];
+        L.v32.d = v[3];
+        L.v32.dinv = v[4];
+        L.v32.tmp1 = v[5];
+        L.v32.tmp2 = v[6];
+    }
     return MFE_OK;
 }
 
-int level_apply(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* w, double* v, hipStream_t s) {
-    const int rc = mfe_apply_tangent(L.ctx, w, v, o->strategy, MFE_FP64, s);
+// out = M_z M_y M_x in for per-axis matrices M (out nodes m[], in nodes n[]),
+// through the two scratch arrays t1, t2 (each at least m_x n_y n_z, m_x m_y n_z)
+template <typename T>
+int tensor_apply(mfe_ctx* c, const DevCSR* M, const T* in, T* t1, T* t2, T* out, hipStream_t s) {
+    const int mx = M[0].rows, my = M[1].rows, mz = M[2].rows;
+    const int nx = M[0].cols, ny = M[1].cols, nz = M[2].cols;
+    T* tag = nullptr;
+    MFE_HIP(c, mfe::launch_axis_csr(M[0].rowptr, M[0].col, M[0].vals(tag), 0, mx, ny, nz, nx, ny, in, t1, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[1].rowptr, M[1].col, M[1].vals(tag), 1, mx, my, nz, mx, ny, t1, t2, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[2].rowptr, M[2].col, M[2].vals(tag), 2, mx, my, mz, mx, my, t2, out, s));
+    return MFE_OK;
+}
+
+template <typename T>
+constexpr int precision_of() {
+    return std::is_same<T, float>::value ? MFE_SF_FP32 : MFE_FP64;
+}
+
+// v = K_l w on level l in the V-cycle's precision and the solve's strategy
+template <typename T>
+int level_apply(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* w, T* v, hipStream_t s) {
+    const int rc = mfe_apply_tangent(L.ctx, w, v, o->strategy, precision_of<T>(), s);
     if (rc != MFE_OK && L.ctx != c) return child_fail(c, L.ctx, rc, "apply");
     return rc;
 }
@@ -944,21 +1072,21 @@ double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) 
 }
 
 // Estimate of lambda_max(D^-1 K) on a level: m steps of Jacobi-preconditioned
-// CG from the level's fixed random right-hand side; the CG coefficients give
-// the Lanczos tridiagonal matrix of D^-1 K, whose largest eigenvalue
-// approaches lambda_max from below.
-int lanczos_lmax(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, hipStream_t s, double& lmax) {
+// CG (FP64, second-order cache) from the level's fixed random right-hand
+// side; the CG coefficients give the Lanczos tridiagonal matrix of D^-1 K,
+// whose largest eigenvalue approaches lambda_max from below.
+int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
     const int64_t n = L.ctx->n_dofs;
     const int m = (int)std::min<int64_t>(24, n);
-    double* x = L.x;
-    double* r = L.b;
-    double* z = L.tmp1;
-    double* pv = L.d;
-    double* Ap = L.r;
+    double* x = L.v64.x;
+    double* r = L.v64.b;
+    double* z = L.v64.tmp1;
+    double* pv = L.v64.d;
+    double* Ap = L.v64.r;
     double* out = c->d_partials + 2 * mfe::kDotBlocks;
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, r, n, s));
-    MFE_HIP(c, mfe::launch_scale_mul(1.0, L.dinv, r, z, n, s));
+    MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, r, z, n, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
     double rr, rz;
     int rc = dotn(c, n, r, r, r, z, s, rr, rz);
@@ -966,8 +1094,8 @@ int lanczos_lmax(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, hipStream_t s,
     std::vector<double> diag, off;
     double alpha_prev = 0.0, beta_prev = 0.0;
     for (int k = 0; k < m; ++k) {
-        rc = level_apply(c, o, L, pv, Ap, s);
-        if (rc != MFE_OK) return rc;
+        rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
+        if (rc != MFE_OK) return L.ctx != c ? child_fail(c, L.ctx, rc, "apply") : rc;
         double pAp, unused;
         rc = dotn(c, n, pv, Ap, nullptr, nullptr, s, pAp, unused);
         if (rc != MFE_OK) return rc;
@@ -975,7 +1103,7 @@ int lanczos_lmax(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, hipStream_t s,
             return fail(c, MFE_ENOTCONV, "eigenvalue estimate: level tangent is not positive definite");
         const double alpha = rz / pAp;
         diag.push_back(1.0 / alpha + (k > 0 ? beta_prev / alpha_prev : 0.0));
-        MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, L.dinv, alpha, n, c->d_partials, out, s));
+        MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, L.v64.dinv, alpha, n, c->d_partials, out, s));
         MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
         const double rz_new = c->h_scalars[1];
@@ -994,39 +1122,50 @@ int lanczos_lmax(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, hipStream_t s,
 }
 
 // Per linearisation point: interpolate the state to every coarser level,
-// build the level caches, the inverse diagonals and an estimate of the
-// largest eigenvalue of D^-1 K (Lanczos, through Jacobi-CG iterations from a
-// fixed random right-hand side).
+// build the level caches (in the V-cycle's precision), the inverse diagonals
+// and an estimate of the largest eigenvalue of D^-1 K.
 int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
     const bool cached = o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD;
+    const bool fp32 = o->mg_precision == MFE_SF_FP32;
+    if (fp32) {
+        const int rc = ensure_mg32(c);
+        if (rc != MFE_OK) return rc;
+    }
     for (size_t l = 0; l < c->mg.size(); ++l) {
         MGLevel& L = c->mg[l];
         mfe_ctx* lc = L.ctx;
         int rc;
         if (l > 0) {
             MGLevel& F = c->mg[l - 1];
-            rc = tensor_apply(c, F.I, F.ctx->d_u, F.tmp1, F.tmp2, L.x, s);
+            rc = tensor_apply(c, F.I, static_cast<const double*>(F.ctx->d_u), F.v64.tmp1, F.v64.tmp2, L.v64.x, s);
             if (rc != MFE_OK) return rc;
-            rc = mfe_set_state(lc, L.x, s);
+            rc = mfe_set_state(lc, L.v64.x, s);
             if (rc != MFE_OK) return child_fail(c, lc, rc, "state");
         }
-        if (cached && (l > 0 || !lc->cache_valid[cache_slot(o->strategy)] ||
-                       lc->cache_version[cache_slot(o->strategy)] != lc->state_version)) {
-            rc = mfe_build_cache(lc, o->strategy, s);
+        if (cached) {
+            const int slot = cache_slot(o->strategy);
+            if (fp32) {
+                rc = mfe_build_cache_fp32(lc, o->strategy, s);
+            } else if (l > 0 || !lc->cache_valid[slot] || (slot > 0 && lc->cache_version[slot] != lc->state_version)) {
+                rc = mfe_build_cache(lc, o->strategy, s);
+            } else {
+                rc = MFE_OK;
+            }
             if (rc != MFE_OK) return l ? child_fail(c, lc, rc, "cache") : rc;
         }
-        rc = diagonal_into(lc, L.dinv, s);
+        rc = diagonal_into(lc, L.v64.dinv, s);
         if (rc != MFE_OK) return l ? child_fail(c, lc, rc, "diagonal") : rc;
         MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
-        MFE_HIP(c, mfe::launch_invert(L.dinv, lc->n_dofs, c->d_bad, s));
+        MFE_HIP(c, mfe::launch_invert(L.v64.dinv, lc->n_dofs, c->d_bad, s));
         int bad = 0;
         MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
         if (bad) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
         double lam = 0.0;
-        rc = lanczos_lmax(c, o, L, s, lam);
+        rc = lanczos_lmax(c, L, s, lam);
         if (rc != MFE_OK) return rc;
         L.lmax = lam;
+        if (fp32) MFE_HIP(c, mfe::launch_convert(L.v64.dinv, L.v32.dinv, lc->n_dofs, s));
     }
     return MFE_OK;
 }
@@ -1034,69 +1173,87 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
 // x = x + p(D^-1 K) D^-1 (b - K x): `degree` Chebyshev-Jacobi steps on
 // [lmax / range, lmax] with lmax 1.2 times the estimate (x = 0 on entry when
 // zero_start, which saves one operator application).
-int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* b, double* x, int degree, double range,
+template <typename T>
+int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* b, T* x, int degree, double range,
               bool zero_start, hipStream_t s) {
+    MGVec<T>& V = L.vecs(static_cast<T*>(nullptr));
     const int64_t n = L.ctx->n_dofs;
     const double hi = 1.2 * L.lmax, lo = hi / range;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     int rc;
     if (zero_start) {
-        MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
-        MFE_HIP(c, mfe::launch_cheb(L.d, x, b, L.dinv, 0.0, 1.0 / theta, n, s));
+        MFE_HIP(c, mfe::launch_fill(x, n, T(0), s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(nullptr), V.dinv, T(0), T(1.0 / theta), n, s));
     } else {
-        rc = level_apply(c, o, L, x, L.r, s);
+        rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
         if (rc != MFE_OK) return rc;
-        MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
-        MFE_HIP(c, mfe::launch_cheb(L.d, x, L.r, L.dinv, 0.0, 1.0 / theta, n, s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(V.r), V.dinv, T(0), T(1.0 / theta), n, s));
     }
     for (int k = 1; k < degree; ++k) {
-        rc = level_apply(c, o, L, x, L.r, s);
+        rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
         if (rc != MFE_OK) return rc;
-        MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        MFE_HIP(c, mfe::launch_cheb(L.d, x, L.r, L.dinv, rho_new * rho, 2.0 * rho_new / delta, n, s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(V.r), V.dinv, T(rho_new * rho),
+                                    T(2.0 * rho_new / delta), n, s));
         rho = rho_new;
     }
     return MFE_OK;
 }
 
 // one V-cycle x = V_l b on level l (x need not be initialised)
-int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const double* b, double* x, hipStream_t s) {
+template <typename T>
+int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipStream_t s) {
     MGLevel& L = c->mg[l];
+    MGVec<T>& V = L.vecs(static_cast<T*>(nullptr));
     mfe_ctx* lc = L.ctx;
     if (l + 1 == c->mg.size()) return chebyshev(c, o, L, b, x, o->coarse_degree, o->coarse_range, true, s);
     int rc = chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, true, s);
     if (rc != MFE_OK) return rc;
     const int64_t n = lc->n_dofs;
-    rc = level_apply(c, o, L, x, L.r, s);
+    rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
     if (rc != MFE_OK) return rc;
-    MFE_HIP(c, mfe::launch_axpby(1.0, b, -1.0, L.r, n, s));
-    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.r, s));
+    MFE_HIP(c, mfe::launch_axpby(T(1), b, T(-1), V.r, n, s));
+    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, T(0), V.r, s));
     MGLevel& C = c->mg[l + 1];
-    rc = tensor_apply(c, L.R, L.r, L.tmp1, L.tmp2, C.b, s);
+    MGVec<T>& CV = C.vecs(static_cast<T*>(nullptr));
+    rc = tensor_apply(c, L.R, static_cast<const T*>(V.r), V.tmp1, V.tmp2, CV.b, s);
     if (rc != MFE_OK) return rc;
-    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, 0.0, C.b, s));
-    rc = vcycle(c, o, l + 1, C.b, C.x, s);
+    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, T(0), CV.b, s));
+    rc = vcycle(c, o, l + 1, static_cast<const T*>(CV.b), CV.x, s);
     if (rc != MFE_OK) return rc;
-    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, 0.0, C.x, s));
-    rc = tensor_apply(c, L.P, C.x, L.tmp1, L.tmp2, L.r, s);  // L.r <- prolongated correction
+    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, T(0), CV.x, s));
+    rc = tensor_apply(c, L.P, static_cast<const T*>(CV.x), V.tmp1, V.tmp2, V.r, s);  // prolongated correction
     if (rc != MFE_OK) return rc;
-    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.r, s));
-    MFE_HIP(c, mfe::launch_axpby(1.0, L.r, 1.0, x, n, s));
+    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, T(0), V.r, s));
+    MFE_HIP(c, mfe::launch_axpby(T(1), static_cast<const T*>(V.r), T(1), x, n, s));
     return chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, false, s);
 }
 
-// z = V r with the GMG hierarchy of c, then r.z
+// z = V r with the GMG hierarchy of c (FP64 or FP32 V-cycle), then r.z
 int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s, double& rz) {
-    int rc = vcycle(c, o, 0, r, z, s);
-    if (rc != MFE_OK) return rc;
+    int rc;
+    if (o->mg_precision == MFE_SF_FP32) {
+        MGLevel& L = c->mg[0];
+        const int64_t n = c->n_dofs;
+        MFE_HIP(c, mfe::launch_convert(r, L.v32.b, n, s));
+        rc = vcycle(c, o, 0, static_cast<const float*>(L.v32.b), L.v32.x, s);
+        if (rc != MFE_OK) return rc;
+        MFE_HIP(c, mfe::launch_convert(static_cast<const float*>(L.v32.x), z, n, s));
+    } else {
+        rc = vcycle(c, o, 0, r, z, s);
+        if (rc != MFE_OK) return rc;
+    }
     double unused;
-    return dot2(c, r, z, nullptr, nullptr, s, rz, unused);
+    rc = dot2(c, r, z, nullptr, nullptr, s, rz, unused);
+    if (rc != MFE_OK) return rc;
+    if (!(rz > 0.0)) return fail(c, MFE_ENOTCONV, "multigrid preconditioner is not positive definite");
+    return MFE_OK;
 }
 
 // preconditioned CG on K(u) x = b, x starts at 0.  Work vectors: r, z, p, Ap, dinv.
-int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStream_t s, int& iters, double& rel) {
+int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStream_t s, int& iters, double& rel,
+       int* fallbacks = nullptr) {
     const int64_t n = c->n_dofs;
     double* r = c->d_work + 0 * n;
     double* z = c->d_work + 1 * n;
@@ -1105,33 +1262,45 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     double* dinv = c->d_work + 4 * n;
     iters = 0;
     rel = 0.0;
-    const bool jac = o->preconditioner == MFE_PC_JACOBI;
-    const bool gmg = o->preconditioner == MFE_PC_GMG;
+    bool jac = o->preconditioner == MFE_PC_JACOBI;
+    bool gmg = o->preconditioner == MFE_PC_GMG;
     int rc;
-    if (gmg) {
-        rc = mg_build(c, o->mg_levels);
-        if (rc != MFE_OK) return rc;
-        rc = mg_update(c, o, s);
-        if (rc != MFE_OK) return rc;
-    }
-    if (jac) {
-        int rc = diagonal_into(c, dinv, s);
-        if (rc != MFE_OK) return rc;
-        MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
-        MFE_HIP(c, mfe::launch_invert(dinv, n, c->d_bad, s));
-        int bad = 0;
-        MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
-        MFE_HIP(c, hipStreamSynchronize(s));
-        if (bad) return fail(c, MFE_EJACOBIAN, "tangent diagonal is not positive: no Jacobi preconditioner");
-    }
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, b, r, n, s));
     if (gmg) {
-        rc = vcycle(c, o, 0, r, z, s);
+        // The V-cycle needs positive level tangents (eigenvalue estimates,
+        // smoothers).  Far from equilibrium K(u) can be indefinite; then this
+        // solve falls back to Jacobi-PCG, which stops at negative curvature
+        // with a descent direction.
+        rc = mg_build(c, o->mg_levels);
         if (rc != MFE_OK) return rc;
-    } else {
-        MFE_HIP(c, mfe::launch_scale_mul(1.0, jac ? dinv : nullptr, r, z, n, s));
+        rc = mg_update(c, o, s);
+        if (rc == MFE_OK) {
+            double unused;
+            rc = gmg_precondition(c, o, r, z, s, unused);
+        }
+        if (rc == MFE_ENOTCONV || rc == MFE_EJACOBIAN) {
+            gmg = false;
+            jac = true;
+            if (fallbacks) ++*fallbacks;
+            c->err.clear();
+        } else if (rc != MFE_OK) {
+            return rc;
+        }
     }
+    if (jac) {
+        // Jacobi with |diag K|: positive (so CG stays well defined) also where
+        // a strongly compressed state makes diagonal entries negative
+        rc = diagonal_into(c, dinv, s);
+        if (rc != MFE_OK) return rc;
+        MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
+        MFE_HIP(c, mfe::launch_invert(dinv, n, c->d_bad, s, true));
+        int bad = 0;
+        MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        if (bad) return fail(c, MFE_EJACOBIAN, "tangent diagonal has zero or non-finite entries: no Jacobi preconditioner");
+    }
+    if (!gmg) MFE_HIP(c, mfe::launch_scale_mul(1.0, jac ? dinv : nullptr, r, z, n, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
     double rr, rz;
     rc = dot2(c, r, r, r, z, s, rr, rz);
@@ -1145,7 +1314,12 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         double pAp, unused;
         rc = dot2(c, pv, Ap, nullptr, nullptr, s, pAp, unused);
         if (rc != MFE_OK) return rc;
-        if (!(pAp > 0.0)) return fail(c, MFE_ENOTCONV, "CG breakdown: p.Kp <= 0 (tangent not positive definite)");
+        if (!(pAp > 0.0)) {
+            // negative curvature: keep the iterate so far; on the first
+            // iteration take the preconditioned residual scaled by |p.Kp|
+            if (it == 1 && pAp < 0.0) MFE_HIP(c, mfe::launch_axpby(rz / -pAp, pv, 0.0, x, n, s));
+            return fail(c, MFE_ENOTCONV, "CG breakdown: p.Kp <= 0 (tangent not positive definite)");
+        }
         const double alpha = rz / pAp;
         MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, jac ? dinv : nullptr, alpha, n, c->d_partials, out, s));
         MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1158,7 +1332,6 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         if (gmg) {
             rc = gmg_precondition(c, o, r, z, s, rz_new);
             if (rc != MFE_OK) return rc;
-            if (!(rz_new > 0.0)) return fail(c, MFE_ENOTCONV, "multigrid preconditioner is not positive definite");
         }
         MFE_HIP(c, mfe::launch_axpby(1.0, z, rz_new / rz, pv, n, s));
         rz = rz_new;
@@ -1249,6 +1422,7 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
     int status = MFE_ENOTCONV;
     double rn = 0.0;
     bool have_res = false;
+    bool boundary_left = has_dg;  // dg holds the part of the Dirichlet increment not yet applied
     for (int it = 0;; ++it) {
         if (!have_res) {
             rc = mfe_residual(c, u, res, s);
@@ -1263,8 +1437,8 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
         local.final_residual = rn;
         if (it < MFE_HISTORY) local.residual_history[it] = rn;
         if (!std::isfinite(rn)) { status = fail(c, MFE_ENOTCONV, "residual is not finite"); break; }
-        const bool first_step_of_load = it == 0 && has_dg;
-        if (!first_step_of_load && rn <= o->newton_atol) { local.converged = 1; status = MFE_OK; break; }
+        const bool boundary_step = boundary_left;
+        if (!boundary_step && rn <= o->newton_atol) { local.converged = 1; status = MFE_OK; break; }
         if (it == o->max_newton) { status = fail(c, MFE_ENOTCONV, "Newton did not converge"); break; }
         rc = mfe_set_state(c, u, s);
         if (rc != MFE_OK) { status = rc; break; }
@@ -1273,7 +1447,7 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
             if (rc != MFE_OK) { status = rc; break; }
         }
         MFE_HIP(c, mfe::launch_scale_mul(-1.0, nullptr, res, res, n, s));
-        if (first_step_of_load) {
+        if (boundary_step) {
             // rhs_f = -R_f - (K dg)_f with the unconstrained operator, rhs_c = dg_c
             rc = apply_impl(c, dg, du, o->strategy, MFE_FP64, false, s);
             if (rc != MFE_OK) { status = rc; break; }
@@ -1282,16 +1456,30 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
         }
         int iters = 0;
         double rel = 0.0;
-        rc = cg(c, o, res, du, s, iters, rel);
+        rc = cg(c, o, res, du, s, iters, rel, &local.pc_fallbacks);
         local.cg_iterations += iters;
         if (rc != MFE_OK && rc != MFE_ENOTCONV) { status = rc; break; }
+        c->err.clear();
         local.newton_iterations = it + 1;
-        if (first_step_of_load) {
+        if (boundary_step) {
+            // the linearised response to the increment is applied in full;
+            // a state it inverts shows as a non-finite residual next
             MFE_HIP(c, mfe::launch_axpby(1.0, du, 1.0, u, n, s));
             MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, g, u, s));  // exact Dirichlet values
+            boundary_left = false;
             continue;
         }
-        // backtracking line search on ||R|| with det F > 0
+        // backtracking line search, det F > 0 required: accept when ||R|| or
+        // the stored energy decreases (Armijo, slope R.du); the energy test
+        // carries the iteration through regions where ||R|| grows on the way
+        // to the minimiser, the residual test the last steps where energy
+        // differences drown in rounding
+        double e0 = 0.0, slope = 0.0, unused0;
+        rc = mfe_energy(c, u, &e0, s);
+        if (rc != MFE_OK) { status = rc; break; }
+        rc = dot2(c, res, du, nullptr, nullptr, s, slope, unused0);  // res holds -R
+        if (rc != MFE_OK) { status = rc; break; }
+        slope = -slope;
         double a = 1.0;
         MFE_HIP(c, mfe::launch_axpby(1.0, du, 1.0, u, n, s));
         bool accepted = false;
@@ -1304,7 +1492,14 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
                 rc = dot2(c, res, res, nullptr, nullptr, s, rr, unused);
                 if (rc != MFE_OK) break;
                 const double rt = std::sqrt(rr);
-                if (rt < rn) {
+                double et = 0.0;
+                bool armijo = false;
+                if (slope < 0.0 && std::isfinite(rt)) {
+                    rc = mfe_energy(c, u, &et, s);
+                    if (rc != MFE_OK) break;
+                    armijo = et <= e0 + 1e-4 * a * slope;
+                }
+                if (rt < rn || (armijo && std::isfinite(rt))) {
                     rn = rt;
                     have_res = true;
                     accepted = true;

@@ -1,4 +1,7 @@
-// Device-side building blocks of the matrix-free tangent (gfx950, FP64).
+// Device-side building blocks of the matrix-free tangent (gfx950).  The
+// sum-factorization kernels and the cached-data point-wise products are
+// templates over the arithmetic type R (double, or float for the mixed-precision
+// sweeps); kinematics and everything that evaluates F, J and log J is FP64.
 //
 //  * 1D sum-factorization kernels with the even-odd split of centro-symmetric
 //    and centro-antisymmetric matrices (the 1D kernels of Sec. 2.4).
@@ -20,6 +23,9 @@
 
 namespace mfe {
 
+MFE_HD double fmar(double a, double b, double c) { return fma(a, b, c); }
+MFE_HD float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+
 // --------------------------------------------------------------------------
 // 1D matrices in even-odd form.
 //
@@ -36,30 +42,30 @@ namespace mfe {
 // and the middle row of odd N is E[N/2][.] = A[N/2][.] (symmetric, acting on
 // x_e) or O[N/2][i] = A[N/2][i] (antisymmetric, acting on x_o).
 // --------------------------------------------------------------------------
-template <int N>
+template <int N, typename R = double>
 struct EO {
     static constexpr int H = (N + 1) / 2;
     static constexpr int M = N / 2;
-    double E[H][H];
-    double O[H][M > 0 ? M : 1];
+    R E[H][H];
+    R O[H][M > 0 ? M : 1];
 };
 
-template <int N>
+template <int N, typename R = double>
 struct Tables {
-    EO<N> S;     // y[q] = sum_i S[q][i] x[i]   nodal values -> Gauss points
-    EO<N> St;    // y[i] = sum_q S[q][i] x[q]   transpose
-    EO<N> D;     // y[q] = sum_l D[q][l] x[l]   derivative collocated on Gauss points
-    EO<N> Dt;    // y[l] = sum_q D[q][l] x[q]   transpose
-    double qp[N];  // Gauss points on [0, 1]
-    double qw[N];  // Gauss weights on [0, 1]
+    EO<N, R> S;     // y[q] = sum_i S[q][i] x[i]   nodal values -> Gauss points
+    EO<N, R> St;    // y[i] = sum_q S[q][i] x[q]   transpose
+    EO<N, R> D;     // y[q] = sum_l D[q][l] x[l]   derivative collocated on Gauss points
+    EO<N, R> Dt;    // y[l] = sum_q D[q][l] x[q]   transpose
+    double qp[N];   // Gauss points on [0, 1]
+    double qw[N];   // Gauss weights on [0, 1]
 };
 
-template <int N, bool ANTI>
-MFE_HD void apply_eo(const EO<N>& T, const double (&x)[N], double (&y)[N]) {
-    constexpr int H = EO<N>::H;
-    constexpr int M = EO<N>::M;
-    double xe[H];
-    double xo[M > 0 ? M : 1];
+template <int N, bool ANTI, typename R>
+MFE_HD void apply_eo(const EO<N, R>& T, const R (&x)[N], R (&y)[N]) {
+    constexpr int H = EO<N, R>::H;
+    constexpr int M = EO<N, R>::M;
+    R xe[H];
+    R xo[M > 0 ? M : 1];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         xe[i] = x[i] + x[N - 1 - i];
@@ -68,11 +74,11 @@ MFE_HD void apply_eo(const EO<N>& T, const double (&x)[N], double (&y)[N]) {
     if constexpr (N % 2 == 1) xe[M] = x[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-        double a = 0.0, b = 0.0;
+        R a = 0, b = 0;
 #pragma unroll
-        for (int i = 0; i < H; ++i) a = fma(T.E[q][i], xe[i], a);
+        for (int i = 0; i < H; ++i) a = fmar(T.E[q][i], xe[i], a);
 #pragma unroll
-        for (int i = 0; i < M; ++i) b = fma(T.O[q][i], xo[i], b);
+        for (int i = 0; i < M; ++i) b = fmar(T.O[q][i], xo[i], b);
         if constexpr (ANTI) {
             y[q] = b + a;
             y[N - 1 - q] = b - a;
@@ -82,13 +88,13 @@ MFE_HD void apply_eo(const EO<N>& T, const double (&x)[N], double (&y)[N]) {
         }
     }
     if constexpr (N % 2 == 1) {
-        double m = 0.0;
+        R m = 0;
         if constexpr (ANTI) {
 #pragma unroll
-            for (int i = 0; i < M; ++i) m = fma(T.O[M][i], xo[i], m);
+            for (int i = 0; i < M; ++i) m = fmar(T.O[M][i], xo[i], m);
         } else {
 #pragma unroll
-            for (int i = 0; i < H; ++i) m = fma(T.E[M][i], xe[i], m);
+            for (int i = 0; i < H; ++i) m = fmar(T.E[M][i], xe[i], m);
         }
         y[M] = m;
     }
@@ -97,21 +103,23 @@ MFE_HD void apply_eo(const EO<N>& T, const double (&x)[N], double (&y)[N]) {
 // --------------------------------------------------------------------------
 // 3x3 algebra (row-major a[i][j])
 // --------------------------------------------------------------------------
-MFE_HD void matmul3(const double a[3][3], const double b[3][3], double c[3][3]) {
+template <typename R>
+MFE_HD void matmul3(const R a[3][3], const R b[3][3], R c[3][3]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            c[i][j] = fma(a[i][0], b[0][j], fma(a[i][1], b[1][j], a[i][2] * b[2][j]));
+            c[i][j] = fmar(a[i][0], b[0][j], fmar(a[i][1], b[1][j], a[i][2] * b[2][j]));
 }
 
 // c = a * b^T
-MFE_HD void matmul3_bt(const double a[3][3], const double b[3][3], double c[3][3]) {
+template <typename R>
+MFE_HD void matmul3_bt(const R a[3][3], const R b[3][3], R c[3][3]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            c[i][j] = fma(a[i][0], b[j][0], fma(a[i][1], b[j][1], a[i][2] * b[j][2]));
+            c[i][j] = fmar(a[i][0], b[j][0], fmar(a[i][1], b[j][1], a[i][2] * b[j][2]));
 }
 
 // adjugate (transpose of the cofactor matrix) and determinant: a^-1 = adj / det
@@ -333,7 +341,8 @@ MFE_HD void kirchhoff_voigt(const double F[3][3], const Kin& k, double mu, doubl
     tau[5] = s * mu * b[0][1];
 }
 
-MFE_HD void tau_full(const double t[6], double T[3][3]) {
+template <typename R>
+MFE_HD void tau_full(const R t[6], R T[3][3]) {
     T[0][0] = t[0]; T[1][1] = t[1]; T[2][2] = t[2];
     T[1][2] = T[2][1] = t[3];
     T[0][2] = T[2][0] = t[4];
@@ -341,18 +350,18 @@ MFE_HD void tau_full(const double t[6], double T[3][3]) {
 }
 
 // T2 point-wise product: h = dw M, g = c1 tr(h) I + c2 sym(h) + h tau, Q = g M^T
-MFE_HD void pointwise_t2(const double dw[3][3], const double M[3][3], const double tau6[6],
-                         double c1, double c2, double Q[3][3]) {
-    double h[3][3], T[3][3], g[3][3];
+template <typename R>
+MFE_HD void pointwise_t2(const R dw[3][3], const R M[3][3], const R tau6[6], R c1, R c2, R Q[3][3]) {
+    R h[3][3], T[3][3], g[3][3];
     matmul3(dw, M, h);
     tau_full(tau6, T);
     matmul3(h, T, g);
-    const double tr = c1 * (h[0][0] + h[1][1] + h[2][2]);
-    const double hc = 0.5 * c2;
+    const R tr = c1 * (h[0][0] + h[1][1] + h[2][2]);
+    const R hc = R(0.5) * c2;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) g[i][j] = fma(hc, h[i][j] + h[j][i], g[i][j]);
+        for (int j = 0; j < 3; ++j) g[i][j] = fmar(hc, h[i][j] + h[j][i], g[i][j]);
     g[0][0] += tr;
     g[1][1] += tr;
     g[2][2] += tr;
@@ -361,19 +370,18 @@ MFE_HD void pointwise_t2(const double dw[3][3], const double M[3][3], const doub
 
 // T4 point-wise product with the general symmetric 6x6 (Voigt) tangent:
 // s = D eps(h) (engineering shears), g = s + h tau, Q = g M^T.
-MFE_HD void pointwise_t4(const double dw[3][3], const double M[3][3], const double D21[21],
-                         const double tau6[6], double Q[3][3]) {
-    double h[3][3], T[3][3], g[3][3];
+template <typename R>
+MFE_HD void pointwise_t4(const R dw[3][3], const R M[3][3], const R D21[21], const R tau6[6], R Q[3][3]) {
+    R h[3][3], T[3][3], g[3][3];
     matmul3(dw, M, h);
-    const double e[6] = {h[0][0], h[1][1], h[2][2], h[1][2] + h[2][1], h[0][2] + h[2][0],
-                         h[0][1] + h[1][0]};
-    double s[6];
+    const R e[6] = {h[0][0], h[1][1], h[2][2], h[1][2] + h[2][1], h[0][2] + h[2][0], h[0][1] + h[1][0]};
+    R s[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
-        double acc = 0.0;
+        R acc = 0;
 #pragma unroll
         for (int c = 0; c < 6; ++c)
-            acc = fma(D21[r <= c ? voigt_packed(r, c) : voigt_packed(c, r)], e[c], acc);
+            acc = fmar(D21[r <= c ? voigt_packed(r, c) : voigt_packed(c, r)], e[c], acc);
         s[r] = acc;
     }
     tau_full(tau6, T);

@@ -1,5 +1,8 @@
 // Cell kernels of the matrix-free tangent, residual, state check and cache
-// construction on gfx950 (FP64).
+// construction on gfx950.  Every kernel exists in FP64; the tangent applies
+// and the T2/T4 cache builds also exist with FP32 input/output vectors and
+// FP32 sum-factorization sweeps (mixed precision: F, J and log J, the
+// geometry and the cached data are computed in FP64 and rounded once).
 //
 // One workgroup processes a brick of neighbouring cells (4x2x2 for Q2), with
 // one thread per quadrature point of the brick for the point-wise work
@@ -15,6 +18,8 @@
 // Gauss points with three sweeps of S (x, y, z), then the reference gradient
 // is taken with the derivative D collocated on the Gauss points; the test
 // contraction applies the transposes in reverse order.
+
+#include <type_traits>
 
 #include "mfe_device.hpp"
 #include "mfe_kernels.hpp"
@@ -143,15 +148,15 @@ __device__ __forceinline__ BrickMap<N> brick_map(const KParams& p, const BrickPo
     return m;
 }
 
-template <int N>
-__device__ __forceinline__ void brick_load(const double* __restrict__ src, const BrickMap<N>& m,
-                                           double (&r)[Geo<N>::GPT]) {
+template <int N, typename R>
+__device__ __forceinline__ void brick_load(const R* __restrict__ src, const BrickMap<N>& m,
+                                           R (&r)[Geo<N>::GPT]) {
 #pragma unroll
-    for (int k = 0; k < Geo<N>::GPT; ++k) r[k] = (m.exists >> k & 1u) ? src[m.dof[k]] : 0.0;
+    for (int k = 0; k < Geo<N>::GPT; ++k) r[k] = (m.exists >> k & 1u) ? src[m.dof[k]] : R(0);
 }
 
-template <int N>
-__device__ __forceinline__ void brick_store(double* sBrick, const double (&r)[Geo<N>::GPT]) {
+template <int N, typename R>
+__device__ __forceinline__ void brick_store(R* sBrick, const R (&r)[Geo<N>::GPT]) {
 #pragma unroll
     for (int k = 0; k < Geo<N>::GPT; ++k) {
         const int e = threadIdx.x + k * Geo<N>::NT;
@@ -176,9 +181,9 @@ __device__ __forceinline__ int gofs(int lc, int idx, int c) {
 // (made visible by a barrier before the call).  On exit slot d of sG holds
 // the reference gradient d field_c / d xi_d at every point.
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<N>& T, double* sG,
-                                               double* sV, double* sBrick, bool clear_brick) {
+template <int N, typename R>
+__device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<N, R>& T, R* sG, R* sV,
+                                               R* sBrick, bool clear_brick) {
     using G = Geo<N>;
     constexpr int N2 = G::N2, P = G::P;
     // x: interpolate every cell's node x-rows -> slot 0 at (qx, j, k)
@@ -187,26 +192,26 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
         const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int j = L.a, k = L.b;
-        const double* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
-        double x[N], y[N];
+        const R* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
+        R x[N], y[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) x[i] = row[3 * i];
         apply_eo<N, false>(T.S, x, y);
-        double* out = sG + gofs<N>(L.lc, N * (j + N * k), L.c);
+        R* out = sG + gofs<N>(L.lc, N * (j + N * k), L.c);
 #pragma unroll
         for (int qx = 0; qx < N; ++qx) out[9 * qx] = y[qx];
     }
     __syncthreads();
     // the brick array is free again: clear it for the backward accumulation
     if (clear_brick)
-        for (int e = threadIdx.x; e < G::BRICK; e += G::NT) sBrick[e] = 0.0;
+        for (int e = threadIdx.x; e < G::BRICK; e += G::NT) sBrick[e] = R(0);
     // y: slot 0 at (qx, j, k) -> slot 1 at (qx, qy, k)
 #pragma unroll
     for (int it = 0; it < G::TPT; ++it) {
         const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-        double x[N], y[N];
+        R x[N], y[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) x[j] = sG[base + 9 * N * j];
         apply_eo<N, false>(T.S, x, y);
@@ -220,7 +225,7 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
         const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
-        double x[N], y[N], dz[N];
+        R x[N], y[N], dz[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) x[k] = sG[base + 9 * N2 * k + 1];
         apply_eo<N, false>(T.S, x, y);
@@ -239,7 +244,7 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
         if (!L.valid) continue;
         {   // x-line at (qy, qz) = (a, b)
             const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
-            double x[N], y[N];
+            R x[N], y[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * l) / 3];
             apply_eo<N, true>(T.D, x, y);
@@ -248,7 +253,7 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
         }
         {   // y-line at (qx, qz) = (a, b)
             const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-            double x[N], y[N];
+            R x[N], y[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * N * l) / 3];
             apply_eo<N, true>(T.D, x, y);
@@ -267,10 +272,9 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
 // with plain stores, nodes on its faces (shared with neighbouring bricks)
 // with FP64 atomics.
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const BrickPos& bp,
-                                                const BrickMap<N>& bm, const Tables<N>& T, double* sG,
-                                                double* sV, double* sBrick) {
+template <int N, typename R>
+__device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const BrickPos& bp, const BrickMap<N>& bm,
+                                                const Tables<N, R>& T, R* sG, R* sV, R* sBrick) {
     using G = Geo<N>;
     constexpr int N2 = G::N2, P = G::P;
     // transposed x- and y-derivatives, in place in slots 0 and 1
@@ -280,7 +284,7 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
         if (!L.valid) continue;
         {
             const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
-            double x[N], y[N];
+            R x[N], y[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * l];
             apply_eo<N, true>(T.Dt, x, y);
@@ -289,7 +293,7 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
         }
         {
             const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-            double x[N], y[N];
+            R x[N], y[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N * l + 1];
             apply_eo<N, true>(T.Dt, x, y);
@@ -305,7 +309,7 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
         const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
-        double x[N], y[N], z[N];
+        R x[N], y[N], z[N];
 #pragma unroll
         for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N2 * l + 2];
         apply_eo<N, true>(T.Dt, x, y);
@@ -322,7 +326,7 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
         const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-        double x[N], y[N];
+        R x[N], y[N];
 #pragma unroll
         for (int qy = 0; qy < N; ++qy) x[qy] = sV[(base + 9 * N * qy) / 3];
         apply_eo<N, false>(T.St, x, y);
@@ -337,11 +341,11 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
         if (!L.valid) continue;
         const int j = L.a, k = L.b;
         const int base = gofs<N>(L.lc, N * (j + N * k), L.c);
-        double x[N], y[N];
+        R x[N], y[N];
 #pragma unroll
         for (int qx = 0; qx < N; ++qx) x[qx] = sG[base + 9 * qx];
         apply_eo<N, false>(T.St, x, y);
-        double* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
+        R* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
 #pragma unroll
         for (int i = 0; i < N; ++i) atomicAdd(row + 3 * i, y[i]);
     }
@@ -349,22 +353,22 @@ __device__ __forceinline__ void backward_sweeps(double* __restrict__ dst, const 
 #pragma unroll
     for (int k = 0; k < G::GPT; ++k) {
         if (!(bm.exists >> k & 1u)) continue;
-        const double val = sBrick[threadIdx.x + k * G::NT];
+        const R val = sBrick[threadIdx.x + k * G::NT];
         if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
         else dst[bm.dof[k]] = val;
     }
 }
 
-template <int N>
-__device__ __forceinline__ void load_slots(const double* sG, int tid, double g[3][3]) {
+template <int N, typename R>
+__device__ __forceinline__ void load_slots(const R* sG, int tid, R g[3][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int d = 0; d < 3; ++d) g[c][d] = sG[(tid * 3 + c) * 3 + d];
 }
 
-template <int N>
-__device__ __forceinline__ void store_slots(double* sG, int tid, const double g[3][3]) {
+template <int N, typename R>
+__device__ __forceinline__ void store_slots(R* sG, int tid, const R g[3][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -385,7 +389,8 @@ template <int MODE>
 struct ModeInfo {
     static constexpr bool fwd_u = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM ||
                                   MODE == MODE_APPLY_OTF_AD || MODE == MODE_RESIDUAL ||
-                                  MODE == MODE_STATE || MODE == MODE_BUILD_T2 || MODE == MODE_BUILD_T4;
+                                  MODE == MODE_STATE || MODE == MODE_BUILD_T2 || MODE == MODE_BUILD_T4 ||
+                                  MODE == MODE_ENERGY;
     static constexpr bool fwd_w = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM ||
                                   MODE == MODE_APPLY_OTF_AD || MODE == MODE_APPLY_T2 ||
                                   MODE == MODE_APPLY_T4;
@@ -393,7 +398,7 @@ struct ModeInfo {
     static constexpr bool vertex_geom = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_AD ||
                                         MODE == MODE_RESIDUAL || MODE == MODE_STATE ||
                                         MODE == MODE_BUILD_GEOM || MODE == MODE_BUILD_T2 ||
-                                        MODE == MODE_BUILD_T4;
+                                        MODE == MODE_BUILD_T4 || MODE == MODE_ENERGY;
     static constexpr int cache_fields = MODE == MODE_APPLY_OTF_GEOM ? kGeomFields
                                       : MODE == MODE_APPLY_T2       ? kT2Fields
                                       : MODE == MODE_APPLY_T4       ? kT4Fields
@@ -403,15 +408,40 @@ struct ModeInfo {
 #ifndef MFE_MIN_WAVES_PER_EU
 #define MFE_MIN_WAVES_PER_EU 1
 #endif
-template <int N, int MODE>
+// Vector and cache element types of a launch: R is the type of w, v, the
+// T2/T4 caches and the sweeps of the w field; the u field, the geometry and
+// the per-point kinematics are always FP64.
+template <typename R>
+__device__ __forceinline__ const R* w_of(const KParams& p) {
+    if constexpr (std::is_same_v<R, float>) return p.w32; else return p.w;
+}
+template <typename R>
+__device__ __forceinline__ R* v_of(const KParams& p) {
+    if constexpr (std::is_same_v<R, float>) return p.v32; else return p.v;
+}
+template <typename R>
+__device__ __forceinline__ const R* cache_of(const KParams& p) {
+    if constexpr (std::is_same_v<R, float>) return p.cache32; else return p.cache;
+}
+template <typename R>
+__device__ __forceinline__ R* cache_out_of(const KParams& p) {
+    if constexpr (std::is_same_v<R, float>) return p.cache_out32; else return p.cache_out;
+}
+
+template <int N, int MODE, typename R>
 __global__ __launch_bounds__(Geo<N>::NT) __attribute__((amdgpu_waves_per_eu(MFE_MIN_WAVES_PER_EU)))
-void cell_kernel(const KParams p, const Tables<N> T) {
+void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
     using G = Geo<N>;
     constexpr int N3 = G::N3;
     using MI = ModeInfo<MODE>;
-    __shared__ double sG[G::NQ * 9];
-    __shared__ double sV[G::NQ * 3];
-    __shared__ double sBrick[G::BRICK];
+    // LDS element type: FP64 whenever the u field is swept, else R
+    using LT = std::conditional_t<MI::fwd_u, double, R>;
+    // type of the cached per-point data read by an apply
+    constexpr bool cached_r = MODE == MODE_APPLY_T2 || MODE == MODE_APPLY_T4;
+    using CT = std::conditional_t<cached_r, R, double>;
+    __shared__ LT sG[G::NQ * 9];
+    __shared__ LT sV[G::NQ * 3];
+    __shared__ LT sBrick[G::BRICK];
     __shared__ double sEdge[G::CPB * 36];
 
     const BrickPos bp = brick_pos(p, G::BX, G::BY, G::BZ, G::P);
@@ -433,14 +463,16 @@ void cell_kernel(const KParams p, const Tables<N> T) {
     auto cidx = [&](int f) { return cbase + (int64_t)f * G::NQ; };
 
     // issue the global loads early: nodal values of the fields, per-point data
-    double ub[G::GPT], wb[G::GPT];
+    double ub[G::GPT];
+    R wb[G::GPT];
     if constexpr (MI::fwd_u) brick_load<N>(p.u, bm, ub);
-    if constexpr (MI::fwd_w) brick_load<N>(p.w, bm, wb);
+    if constexpr (MI::fwd_w) brick_load<N>(w_of<R>(p), bm, wb);
     constexpr int NCF = MI::cache_fields > 0 ? MI::cache_fields : 1;
-    double cf[NCF];
+    CT cf[NCF];
     if constexpr (MI::cache_fields > 0) {
+        const CT* cache = cached_r ? (const CT*)cache_of<R>(p) : (const CT*)p.cache;
 #pragma unroll
-        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? p.cache[cidx(f)] : 0.0;
+        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? cache[cidx(f)] : CT(0);
     }
 
     if constexpr (MI::vertex_geom) {
@@ -493,11 +525,12 @@ void cell_kernel(const KParams p, const Tables<N> T) {
     double F[3][3] = {};
     double du[3][3] = {};
     if constexpr (MI::fwd_u) {
-        brick_store<N>(sBrick, ub);
+        brick_store<N>(reinterpret_cast<double*>(sBrick), ub);
         __syncthreads();
-        forward_sweeps<N>(bp, T, sG, sV, sBrick, !MI::fwd_w);
+        forward_sweeps<N>(bp, T, reinterpret_cast<double*>(sG), reinterpret_cast<double*>(sV),
+                          reinterpret_cast<double*>(sBrick), !MI::fwd_w);
         if (active) {
-            load_slots<N>(sG, tid, du);
+            load_slots<N>(reinterpret_cast<const double*>(sG), tid, du);
             if constexpr (MODE == MODE_APPLY_OTF_GEOM) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -519,66 +552,104 @@ void cell_kernel(const KParams p, const Tables<N> T) {
         return;
     }
 
+    if constexpr (MODE == MODE_ENERGY) {
+        // stored energy of the compressible neo-Hookean law, summed over the
+        // brick's points in a fixed order (one partial per brick)
+        __shared__ double sRed[G::NT / 64];
+        double e = 0.0;
+        if (active) {
+            double trC = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) trC = fma(F[i][j], F[i][j], trC);
+            e = (0.5 * mu * (trC - 3.0 - 2.0 * kin.lJ) + lam * kin.lJ * kin.lJ) * JxW;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
+        if ((tid & 63) == 0) sRed[tid >> 6] = e;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < G::NT / 64; ++w) sum += sRed[w];
+            p.v[bp.brick] = sum;
+        }
+        return;
+    }
+
     if constexpr (MODE == MODE_BUILD_T2 || MODE == MODE_BUILD_T4) {
         if (active) {
+            R* out = cache_out_of<R>(p);
             double M[3][3], tau[6];
             spatial_map(Jinv, kin, M);
             kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
             if constexpr (MODE == MODE_BUILD_T2) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[cidx(i)] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) out[cidx(i)] = (R)M[i / 3][i % 3];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[cidx(9 + i)] = tau[i];
-                p.cache_out[cidx(15)] = 2.0 * lam * JxW;
-                p.cache_out[cidx(16)] = 2.0 * (mu - 2.0 * lam * kin.lJ) * JxW;
+                for (int i = 0; i < 6; ++i) out[cidx(9 + i)] = (R)tau[i];
+                out[cidx(15)] = (R)(2.0 * lam * JxW);
+                out[cidx(16)] = (R)(2.0 * (mu - 2.0 * lam * kin.lJ) * JxW);
             } else {
                 double D21[21];
                 spatial_tangent_voigt(kin, mu, lam, JxW, D21);
 #pragma unroll
-                for (int i = 0; i < 21; ++i) p.cache_out[cidx(i)] = D21[i];
+                for (int i = 0; i < 21; ++i) out[cidx(i)] = (R)D21[i];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) p.cache_out[cidx(21 + i)] = tau[i];
+                for (int i = 0; i < 6; ++i) out[cidx(21 + i)] = (R)tau[i];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) p.cache_out[cidx(27 + i)] = M[i / 3][i % 3];
+                for (int i = 0; i < 9; ++i) out[cidx(27 + i)] = (R)M[i / 3][i % 3];
             }
         }
         return;
     }
 
     // ---------------- field w and the point-wise product
-    double Q[3][3] = {};
+    R* gW = reinterpret_cast<R*>(sG);
+    R* vW = reinterpret_cast<R*>(sV);
+    R* bW = reinterpret_cast<R*>(sBrick);
+    R Q[3][3] = {};
     if constexpr (MI::fwd_w) {
         // sBrick was last read before the forward sweeps' first barrier
-        brick_store<N>(sBrick, wb);
+        brick_store<N>(bW, wb);
         __syncthreads();
-        forward_sweeps<N>(bp, T, sG, sV, sBrick, true);
+        forward_sweeps<N>(bp, TR, gW, vW, bW, true);
         if (active) {
-            double dw[3][3];
-            load_slots<N>(sG, tid, dw);
-            if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM) {
-                pointwise_otf(dw, Jinv, kin, mu, lam, JxW, Q);
-            } else if constexpr (MODE == MODE_APPLY_OTF_AD) {
-                pointwise_otf_ad(du, dw, Jinv, mu, lam, JxW, Q);
+            R dwr[3][3];
+            load_slots<N>(gW, tid, dwr);
+            if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || MODE == MODE_APPLY_OTF_AD) {
+                // the point-wise response is evaluated in FP64
+                double dw[3][3], Qd[3][3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) dw[i][j] = dwr[i][j];
+                if constexpr (MODE == MODE_APPLY_OTF_AD) pointwise_otf_ad(du, dw, Jinv, mu, lam, JxW, Qd);
+                else pointwise_otf(dw, Jinv, kin, mu, lam, JxW, Qd);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Q[i][j] = (R)Qd[i][j];
             } else if constexpr (MODE == MODE_APPLY_T2) {
-                const double M[3][3] = {{cf[0], cf[1], cf[2]}, {cf[3], cf[4], cf[5]}, {cf[6], cf[7], cf[8]}};
-                const double tau[6] = {cf[9], cf[10], cf[11], cf[12], cf[13], cf[14]};
-                pointwise_t2(dw, M, tau, cf[15], cf[16], Q);
+                const R M[3][3] = {{cf[0], cf[1], cf[2]}, {cf[3], cf[4], cf[5]}, {cf[6], cf[7], cf[8]}};
+                const R tau[6] = {cf[9], cf[10], cf[11], cf[12], cf[13], cf[14]};
+                pointwise_t2(dwr, M, tau, cf[15], cf[16], Q);
             } else if constexpr (MODE == MODE_APPLY_T4) {
-                const double M[3][3] = {{cf[27], cf[28], cf[29]}, {cf[30], cf[31], cf[32]},
-                                        {cf[33], cf[34], cf[35]}};
-                const double tau[6] = {cf[21], cf[22], cf[23], cf[24], cf[25], cf[26]};
-                pointwise_t4(dw, M, cf, tau, Q);
+                const R M[3][3] = {{cf[27], cf[28], cf[29]}, {cf[30], cf[31], cf[32]}, {cf[33], cf[34], cf[35]}};
+                const R tau[6] = {cf[21], cf[22], cf[23], cf[24], cf[25], cf[26]};
+                pointwise_t4(dwr, M, cf, tau, Q);
             }
         }
     } else if constexpr (MODE == MODE_RESIDUAL) {
+        static_assert(std::is_same_v<R, double>, "the residual is FP64 only");
         if (active) pointwise_piola(F, kin, mu, lam, Jinv, JxW, Q);
     }
 
     if constexpr (MI::backward) {
         // each thread overwrites only its own point's slots, which only it read
-        if (active) store_slots<N>(sG, tid, Q);
+        if (active) store_slots<N>(gW, tid, Q);
         __syncthreads();
-        backward_sweeps<N>(p.v, bp, bm, T, sG, sV, sBrick);
+        backward_sweeps<N>(v_of<R>(p), bp, bm, TR, gW, vW, bW);
     }
 }
 
@@ -682,27 +753,65 @@ static Tables<N> make_tables(const Tables1D& t) {
     return T;
 }
 
-template <int N, int MODE>
+template <int N>
+static Tables<N, float> to_float(const Tables<N>& T) {
+    Tables<N, float> F;
+    auto cvt = [](const EO<N>& a, EO<N, float>& b) {
+        for (int q = 0; q < EO<N>::H; ++q) {
+            for (int i = 0; i < EO<N>::H; ++i) b.E[q][i] = (float)a.E[q][i];
+            for (int i = 0; i < (EO<N>::M > 0 ? EO<N>::M : 1); ++i) b.O[q][i] = (float)a.O[q][i];
+        }
+    };
+    cvt(T.S, F.S);
+    cvt(T.St, F.St);
+    cvt(T.D, F.D);
+    cvt(T.Dt, F.Dt);
+    for (int i = 0; i < N; ++i) {
+        F.qp[i] = T.qp[i];
+        F.qw[i] = T.qw[i];
+    }
+    return F;
+}
+
+template <int N, int MODE, typename R>
 static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream) {
     const int nb = p.nbx * p.nby * p.nbz;
-    hipLaunchKernelGGL((cell_kernel<N, MODE>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T);
+    if constexpr (std::is_same_v<R, float>) {
+        const Tables<N, float> TF = to_float<N>(T);
+        hipLaunchKernelGGL((cell_kernel<N, MODE, float>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, TF);
+    } else {
+        hipLaunchKernelGGL((cell_kernel<N, MODE, double>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, T);
+    }
     return hipGetLastError();
 }
 
 template <int N>
-static hipError_t launch_n(int mode, const Tables1D& t, const KParams& p, hipStream_t s) {
+static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s) {
     const Tables<N> T = make_tables<N>(t);
+    if (fp32) {
+        switch (mode) {
+            case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float>(T, p, s);
+            case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float>(T, p, s);
+            case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float>(T, p, s);
+            case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float>(T, p, s);
+            case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float>(T, p, s);
+            case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, float>(T, p, s);
+            case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, float>(T, p, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (mode) {
-        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF>(T, p, s);
-        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM>(T, p, s);
-        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2>(T, p, s);
-        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4>(T, p, s);
-        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD>(T, p, s);
-        case MODE_RESIDUAL: return launch_nm<N, MODE_RESIDUAL>(T, p, s);
-        case MODE_STATE: return launch_nm<N, MODE_STATE>(T, p, s);
-        case MODE_BUILD_GEOM: return launch_nm<N, MODE_BUILD_GEOM>(T, p, s);
-        case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2>(T, p, s);
-        case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4>(T, p, s);
+        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, double>(T, p, s);
+        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, double>(T, p, s);
+        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, double>(T, p, s);
+        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, double>(T, p, s);
+        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, double>(T, p, s);
+        case MODE_RESIDUAL: return launch_nm<N, MODE_RESIDUAL, double>(T, p, s);
+        case MODE_STATE: return launch_nm<N, MODE_STATE, double>(T, p, s);
+        case MODE_BUILD_GEOM: return launch_nm<N, MODE_BUILD_GEOM, double>(T, p, s);
+        case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, double>(T, p, s);
+        case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, double>(T, p, s);
+        case MODE_ENERGY: return launch_nm<N, MODE_ENERGY, double>(T, p, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -748,15 +857,15 @@ hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hi
     }
 }
 
-hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream) {
+hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32) {
     if (p.ne <= 0) return hipSuccess;
     switch (t.n) {
-        case 2: return launch_n<2>(mode, t, p, stream);
-        case 3: return launch_n<3>(mode, t, p, stream);
-        case 4: return launch_n<4>(mode, t, p, stream);
-        case 5: return launch_n<5>(mode, t, p, stream);
-        case 6: return launch_n<6>(mode, t, p, stream);
-        case 7: return launch_n<7>(mode, t, p, stream);
+        case 2: return launch_n<2>(mode, fp32, t, p, stream);
+        case 3: return launch_n<3>(mode, fp32, t, p, stream);
+        case 4: return launch_n<4>(mode, fp32, t, p, stream);
+        case 5: return launch_n<5>(mode, fp32, t, p, stream);
+        case 6: return launch_n<6>(mode, fp32, t, p, stream);
+        case 7: return launch_n<7>(mode, fp32, t, p, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -764,19 +873,21 @@ hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hip
 // ---------------------------------------------------------------------------
 // Small vector kernels
 // ---------------------------------------------------------------------------
-__global__ void fill_kernel(double* __restrict__ x, int64_t n, double value) {
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ x, int64_t n, T value) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = value;
 }
 
-__global__ void copy_indexed_kernel(const int64_t* __restrict__ idx, int64_t n,
-                                    const double* __restrict__ src, double* __restrict__ dst) {
+template <typename T>
+__global__ void copy_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, const T* __restrict__ src,
+                                    T* __restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[idx[i]] = src[idx[i]];
 }
 
-__global__ void set_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, double value,
-                                   double* __restrict__ dst) {
+template <typename T>
+__global__ void set_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, T value, T* __restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[idx[i]] = value;
 }
@@ -795,27 +906,43 @@ hipError_t launch_diff_indexed(const int64_t* idx, int64_t n, const double* a, c
     return hipGetLastError();
 }
 
-hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream) {
+template <typename T>
+static hipError_t fill_t(T* x, int64_t n, T value, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, value);
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, value);
     return hipGetLastError();
 }
+hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t s) { return fill_t(x, n, value, s); }
+hipError_t launch_fill(float* x, int64_t n, float value, hipStream_t s) { return fill_t(x, n, value, s); }
 
-hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
-                               hipStream_t stream) {
+template <typename T>
+static hipError_t copy_indexed_t(const int64_t* idx, int64_t n, const T* src, T* dst, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(copy_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
+    hipLaunchKernelGGL(copy_indexed_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
                        src, dst);
     return hipGetLastError();
 }
+hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst, hipStream_t s) {
+    return copy_indexed_t(idx, n, src, dst, s);
+}
+hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const float* src, float* dst, hipStream_t s) {
+    return copy_indexed_t(idx, n, src, dst, s);
+}
 
-hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t stream) {
+template <typename T>
+static hipError_t set_indexed_t(const int64_t* idx, int64_t n, T value, T* dst, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(set_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
+    hipLaunchKernelGGL(set_indexed_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n,
                        value, dst);
     return hipGetLastError();
+}
+hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t s) {
+    return set_indexed_t(idx, n, value, dst, s);
+}
+hipError_t launch_set_indexed(const int64_t* idx, int64_t n, float value, float* dst, hipStream_t s) {
+    return set_indexed_t(idx, n, value, dst, s);
 }
 
 }  // namespace mfe

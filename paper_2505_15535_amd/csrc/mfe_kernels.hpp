@@ -18,7 +18,8 @@ enum Mode : int {
     MODE_BUILD_GEOM = 7,      // cache <- (Jg^-1, JxW)
     MODE_BUILD_T2 = 8,        // cache <- (M, tau JxW, c1, c2)
     MODE_BUILD_T4 = 9,        // cache <- (Jc JxW, tau JxW, M)
-    MODE_COUNT = 10
+    MODE_ENERGY = 10,         // v[brick] <- sum over the brick's points of JxW psi(F)
+    MODE_COUNT = 11
 };
 
 // Doubles per quadrature point of each cache.
@@ -38,6 +39,10 @@ struct KParams {
     double* v;                 // output, accumulated with atomics
     const double* cache;       // SoA cache read by OTF_GEOM/T2/T4 applies
     double* cache_out;         // SoA cache written by BUILD modes
+    const float* w32;          // FP32 launches: input vector
+    float* v32;                // FP32 launches: output vector
+    const float* cache32;      // FP32 T2/T4 applies: cache (OTF_GEOM reads `cache`)
+    float* cache_out32;        // FP32 T2/T4 builds: cache written
     const double* cell_mat;    // ne x (mu, lambda) or null
     double mu, lam;            // uniform material
     int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
@@ -58,8 +63,11 @@ struct Tables1D {
 // n = p+1 points per direction (zeros for an unsupported n).
 void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick);
 
-// Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).
-hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream);
+// Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).  With
+// fp32 the w/v vectors (w32, v32), the T2/T4 caches (cache32, cache_out32)
+// and the sweeps of w are FP32; only the apply and T2/T4 build modes exist so.
+hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream,
+                              bool fp32 = false);
 
 // Nodal basis values S and their derivatives Sd at the Gauss points.
 struct DiagTables {
@@ -72,6 +80,7 @@ struct DiagTables {
 hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
 
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream);
+hipError_t launch_fill(float* x, int64_t n, float value, hipStream_t stream);
 
 // Solver vector kernels.  Reductions use kDotBlocks partial sums (scratch of
 // 2*kDotBlocks doubles) and a fixed-order second pass, so they are
@@ -83,22 +92,35 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
                             double alpha, int64_t n, double* partials, double* out, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
-hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s);
+// d = 1/d (1/|d| with absolute); *bad = 1 where that is not positive and finite
+// out[0] = sum of x[0..n) (one workgroup, fixed order)
+hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
+hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s, bool absolute = false);
 
-// Multigrid kernels.  out = M in with the 1D CSR matrix M acting along `axis`
-// of nodal arrays [nz][ny][nx][3] (out extents nx_out, ny_out, nz_out; in has
-// nx_in, ny_in and the out extents elsewhere).
+// Multigrid kernels (FP64 and FP32).  out = M in with the 1D CSR matrix M
+// acting along `axis` of nodal arrays [nz][ny][nx][3] (out extents nx_out,
+// ny_out, nz_out; in has nx_in, ny_in and the out extents elsewhere).
 hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* vals, int axis, int nx_out,
                            int ny_out, int nz_out, int nx_in, int ny_in, const double* in, double* out,
                            hipStream_t s);
-// d = c1 d + c2 dinv .* r;  x += d  (d is not read when c1 = 0)
-hipError_t launch_cheb(double* d, double* x, const double* r, const double* dinv, double c1, double c2, int64_t n,
-                       hipStream_t s);
+hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const float* vals, int axis, int nx_out,
+                           int ny_out, int nz_out, int nx_in, int ny_in, const float* in, float* out,
+                           hipStream_t s);
+// d = c1 d + c2 dinv .* (b - Ax);  x += d  (Ax null: b; d is not read when c1 = 0)
+hipError_t launch_cheb(double* d, double* x, const double* b, const double* Ax, const double* dinv, double c1,
+                       double c2, int64_t n, hipStream_t s);
+hipError_t launch_cheb(float* d, float* x, const float* b, const float* Ax, const float* dinv, float c1, float c2,
+                       int64_t n, hipStream_t s);
+hipError_t launch_axpby(float a, const float* x, float b, float* y, int64_t n, hipStream_t s);
+hipError_t launch_convert(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_convert(const float* src, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
                                hipStream_t stream);
+hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const float* src, float* dst, hipStream_t stream);
 // dst[idx[i]] = a[idx[i]] - b[idx[i]]
 hipError_t launch_diff_indexed(const int64_t* idx, int64_t n, const double* a, const double* b, double* dst,
                                hipStream_t stream);
 hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t stream);
+hipError_t launch_set_indexed(const int64_t* idx, int64_t n, float value, float* dst, hipStream_t stream);
 
 }  // namespace mfe

@@ -1,7 +1,8 @@
 // Kernels of the geometric multigrid preconditioner (Sec. 2.3): grid
 // transfers between nested Q_p boxes as tensor products of 1D matrices
 // (prolongation, restriction, interpolation of the linearisation point to the
-// coarser level), and the Chebyshev-Jacobi smoother update.
+// coarser level), the Chebyshev-Jacobi smoother update and the precision
+// conversions of the mixed-precision V-cycle.  FP64 and FP32 instances.
 
 #include <hip/hip_runtime.h>
 
@@ -11,9 +12,10 @@ namespace mfe {
 
 // out = M_axis in, where M (rows x cols, CSR) acts along `axis` of nodal
 // arrays [nz][ny][nx][3]; the other two extents are shared by in and out.
+template <typename T>
 __global__ void axis_csr_kernel(const int* __restrict__ rowptr, const int* __restrict__ colidx,
-                                const double* __restrict__ vals, int axis, int nx_out, int ny_out, int nz_out,
-                                int nx_in, int ny_in, const double* __restrict__ in, double* __restrict__ out) {
+                                const T* __restrict__ vals, int axis, int nx_out, int ny_out, int nz_out,
+                                int nx_in, int ny_in, const T* __restrict__ in, T* __restrict__ out) {
     const int64_t n = (int64_t)nx_out * ny_out * nz_out * 3;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
@@ -24,7 +26,7 @@ __global__ void axis_csr_kernel(const int* __restrict__ rowptr, const int* __res
         const int j = (int)(r % ny_out);
         const int k = (int)(r / ny_out);
         const int row = axis == 0 ? i : (axis == 1 ? j : k);
-        double s = 0.0;
+        T s = 0;
         for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) {
             const int col = colidx[e];
             const int ii = axis == 0 ? col : i, jj = axis == 1 ? col : j, kk = axis == 2 ? col : k;
@@ -34,16 +36,33 @@ __global__ void axis_csr_kernel(const int* __restrict__ rowptr, const int* __res
     }
 }
 
-// Chebyshev step: d = c1 d + c2 dinv .* r;  x += d  (d is not read when c1 = 0)
-__global__ void cheb_kernel(double* __restrict__ d, double* __restrict__ x, const double* __restrict__ r,
-                            const double* __restrict__ dinv, double c1, double c2, int64_t n) {
+// Chebyshev step with the residual formed on the fly:
+//   d = c1 d + c2 dinv .* (b - Ax);  x += d
+// (Ax null: residual b; c1 = 0: d is not read).
+template <typename T>
+__global__ void cheb_kernel(T* __restrict__ d, T* __restrict__ x, const T* __restrict__ b,
+                            const T* __restrict__ Ax, const T* __restrict__ dinv, T c1, T c2, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double step = c2 * dinv[i] * r[i];
-        const double di = c1 == 0.0 ? step : fma(c1, d[i], step);
+        const T r = Ax ? b[i] - Ax[i] : b[i];
+        const T step = c2 * dinv[i] * r;
+        const T di = c1 == T(0) ? step : fma(c1, d[i], step);
         d[i] = di;
         x[i] += di;
     }
+}
+
+// y = a x + b y
+template <typename T>
+__global__ void axpby_t_kernel(T a, const T* __restrict__ x, T b, T* __restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = fma(a, x[i], b * y[i]);
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (D)src[i];
 }
 
 static unsigned grid_of(int64_t n) {
@@ -51,18 +70,51 @@ static unsigned grid_of(int64_t n) {
     return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
-hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* vals, int axis, int nx_out,
-                           int ny_out, int nz_out, int nx_in, int ny_in, const double* in, double* out,
-                           hipStream_t s) {
+template <typename T>
+static hipError_t axis_csr_t(const int* rowptr, const int* colidx, const T* vals, int axis, int nx_out, int ny_out,
+                             int nz_out, int nx_in, int ny_in, const T* in, T* out, hipStream_t s) {
     const int64_t n = (int64_t)nx_out * ny_out * nz_out * 3;
-    hipLaunchKernelGGL(axis_csr_kernel, dim3(grid_of(n)), dim3(256), 0, s, rowptr, colidx, vals, axis, nx_out,
+    hipLaunchKernelGGL(axis_csr_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, rowptr, colidx, vals, axis, nx_out,
                        ny_out, nz_out, nx_in, ny_in, in, out);
     return hipGetLastError();
 }
+hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* vals, int axis, int nx_out,
+                           int ny_out, int nz_out, int nx_in, int ny_in, const double* in, double* out,
+                           hipStream_t s) {
+    return axis_csr_t(rowptr, colidx, vals, axis, nx_out, ny_out, nz_out, nx_in, ny_in, in, out, s);
+}
+hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const float* vals, int axis, int nx_out,
+                           int ny_out, int nz_out, int nx_in, int ny_in, const float* in, float* out,
+                           hipStream_t s) {
+    return axis_csr_t(rowptr, colidx, vals, axis, nx_out, ny_out, nz_out, nx_in, ny_in, in, out, s);
+}
 
-hipError_t launch_cheb(double* d, double* x, const double* r, const double* dinv, double c1, double c2, int64_t n,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(cheb_kernel, dim3(grid_of(n)), dim3(256), 0, s, d, x, r, dinv, c1, c2, n);
+template <typename T>
+static hipError_t cheb_t(T* d, T* x, const T* b, const T* Ax, const T* dinv, T c1, T c2, int64_t n,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(cheb_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, d, x, b, Ax, dinv, c1, c2, n);
+    return hipGetLastError();
+}
+hipError_t launch_cheb(double* d, double* x, const double* b, const double* Ax, const double* dinv, double c1,
+                       double c2, int64_t n, hipStream_t s) {
+    return cheb_t(d, x, b, Ax, dinv, c1, c2, n, s);
+}
+hipError_t launch_cheb(float* d, float* x, const float* b, const float* Ax, const float* dinv, float c1, float c2,
+                       int64_t n, hipStream_t s) {
+    return cheb_t(d, x, b, Ax, dinv, c1, c2, n, s);
+}
+
+hipError_t launch_axpby(float a, const float* x, float b, float* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_t_kernel<float>, dim3(grid_of(n)), dim3(256), 0, s, a, x, b, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const double* src, float* dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid_of(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_convert(const float* src, double* dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_of(n)), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -61,6 +61,16 @@ __global__ __launch_bounds__(kRedThreads) void reduce2_kernel(const double* __re
     }
 }
 
+// out[0] = sum of x (single workgroup, fixed order)
+__global__ __launch_bounds__(kRedThreads) void sum_kernel(const double* __restrict__ x, int64_t n,
+                                                          double* __restrict__ out) {
+    __shared__ double sh[kRedThreads / 64];
+    double s0 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s0 += x[i];
+    const double t0 = block_sum(s0, sh);
+    if (threadIdx.x == 0) out[0] = t0;
+}
+
 // x += alpha p; r -= alpha Ap; z = dinv .* r (z = r without dinv); partial (r.r, r.z)
 __global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
                                                                 double* __restrict__ z, const double* __restrict__ p,
@@ -101,11 +111,12 @@ __global__ void scale_mul_kernel(double scale, const double* __restrict__ s, con
         y[i] = scale * (s ? s[i] * x[i] : x[i]);
 }
 
-// d = 1 / d (entries that are not positive and finite are an error for Jacobi)
-__global__ void invert_kernel(double* __restrict__ d, int64_t n, int* __restrict__ bad) {
+// d = 1 / d, or 1 / |d| with `absolute`; entries that are not positive
+// (after the absolute value) and finite set *bad
+__global__ void invert_kernel(double* __restrict__ d, int64_t n, int* __restrict__ bad, bool absolute) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double v = d[i];
+        const double v = absolute ? fabs(d[i]) : d[i];
         if (!(v > 0.0) || !(v < 1e300)) atomicOr(bad, 1);
         d[i] = 1.0 / v;
     }
@@ -133,6 +144,11 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
     return hipGetLastError();
 }
 
+hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kRedThreads), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, x, b, y, n);
     return hipGetLastError();
@@ -143,8 +159,8 @@ hipError_t launch_scale_mul(double scale, const double* sc, const double* x, dou
     return hipGetLastError();
 }
 
-hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s) {
-    hipLaunchKernelGGL(invert_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, d, n, bad);
+hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s, bool absolute) {
+    hipLaunchKernelGGL(invert_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, d, n, bad, absolute);
     return hipGetLastError();
 }
 

@@ -110,6 +110,32 @@ def test_residual_parity(torch_dev):
     assert _rel(r, ref) <= TOL
 
 
+def test_energy_parity(torch_dev):
+    """Stored energy against the oracle (uniform and per-cell material), its
+    directional derivative against the residual, and a non-finite value for
+    an inverted state."""
+    torch, _ = torch_dev
+    cfg = synthetic.get_config("cube4_q2_jit")
+    verts, u, w = cfg.vertices(), cfg.displacement(), cfg.test_vector(1)
+    mesh = BoxMesh(cfg.nx, cfg.ny, cfg.nz, cfg.degree, verts)
+    P = Problem(mesh, cfg.mu, cfg.lam)
+    op = _op(torch_dev, cfg.nx, cfg.ny, cfg.nz, cfg.degree, verts, cfg.mu, cfg.lam)
+    ud = _to(torch_dev, u)
+    e = op.energy(ud)
+    assert abs(e - P.energy(u)) <= 1e-12 * abs(P.energy(u))
+    eps = 1e-6
+    de = (op.energy(ud + eps * _to(torch_dev, w)) - op.energy(ud - eps * _to(torch_dev, w))) / (2 * eps)
+    rw = float(np.dot(op.residual(ud).cpu().numpy(), w))
+    assert abs(de - rw) <= 1e-6 * abs(rw)
+    ml = np.tile([cfg.mu, cfg.lam], (cfg.n_elems, 1))
+    ml[::3] *= 50.0
+    Pc = Problem(mesh, 0.0, 0.0, elem_mu_lam=ml)
+    opc = _op(torch_dev, cfg.nx, cfg.ny, cfg.nz, cfg.degree, verts, 1.0, 1.0, per_cell=ml)
+    assert abs(opc.energy(ud) - Pc.energy(u)) <= 1e-12 * abs(Pc.energy(u))
+    X = mesh.node_positions()
+    assert not np.isfinite(op.energy(_to(torch_dev, (-2.0 * X).reshape(-1))))
+
+
 def test_constraints_parity(torch_dev):
     cfg = synthetic.get_config("cube4_q2_jit")
     verts, u, W = cfg.vertices(), cfg.displacement(), cfg.test_vectors()[:2]

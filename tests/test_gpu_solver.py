@@ -105,6 +105,37 @@ def test_gmg_cg_beats_jacobi(torch_dev, levels):
     assert np.linalg.norm(xg2.cpu().numpy() - xg) / np.linalg.norm(xg) <= 1e-9
 
 
+def test_gmg_fp32_vcycle_defect_correction(torch_dev):
+    """FP32 V-cycle inside the FP64 CG: the outer iteration still reaches a
+    relative residual of 1e-10 (the FP32 preconditioner only changes the
+    search directions), with about as many iterations as the FP64 V-cycle."""
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz, L = 16, 4, 4, (4.0, 1.0, 1.0)
+    verts = synthetic.box_vertices(nx, ny, nz, L, jitter=0.15, rng=synthetic.rng_for(90, 0))
+    cdofs, vals = synthetic.clamp_and_twist(nx, ny, nz, 2, L, np.deg2rad(5.0))
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, 10.0, device=0)
+    op.set_constraints(cdofs)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
+    u[torch.from_numpy(cdofs).to(dev)] = _to(torch_dev, vals)
+    op.set_state(u)
+    b = synthetic.random_vectors(op.n_dofs, 1, synthetic.rng_for(90, 2))[0]
+    b[cdofs] = 0.0
+    bt = _to(torch_dev, b)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        for strategy in ("t2", "otf"):
+            x, it, rel, st = op.cg_solve(bt, strategy=strategy, preconditioner="gmg", mg_precision=prec,
+                                         max_cg=5000, cg_rtol=1e-10)
+            assert st == "MFE_OK" and rel <= 1e-10, (prec, strategy, st, op.last_error())
+            res[prec, strategy] = (x.cpu().numpy(), it)
+    print({k: v[1] for k, v in res.items()})
+    x64 = res["fp64", "t2"][0]
+    for k, (x, it) in res.items():
+        assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 1e-8, k
+        assert it <= 1.25 * res["fp64", "t2"][1] + 2, k
+
+
 def test_gmg_per_cell_material_and_options(torch_dev):
     """Per-cell (mu, lambda) averaged onto the coarse levels; option checks."""
     import paper_2505_15535_amd as mfe
@@ -133,7 +164,7 @@ def test_gmg_per_cell_material_and_options(torch_dev):
     assert status == "MFE_OK" and it < 60
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
     for bad in ({"cheb_degree": 0}, {"cheb_range": 1.0}, {"coarse_degree": 0}, {"coarse_range": float("nan")},
-                {"mg_levels": -1}):
+                {"mg_levels": -1}, {"mg_precision": 2}):
         with pytest.raises(mfe.MfeError, match="MFE_EINVAL"):
             op.cg_solve(_to(torch_dev, b), preconditioner="gmg", **bad)
 
@@ -170,9 +201,10 @@ def test_newton_twisted_beam_parity(torch_dev):
     assert np.linalg.norm(P.residual(ug)) <= 1e-9
 
 
-def test_newton_twisted_beam_gmg(torch_dev):
-    """The same load path with the GMG preconditioner (8x2x2 -> 4x1x1) and
-    the fourth-order cache: converges to the oracle's solution."""
+@pytest.mark.parametrize("strategy,mg_precision", [("t4", "fp64"), ("t2", "fp32")])
+def test_newton_twisted_beam_gmg(torch_dev, strategy, mg_precision):
+    """The same load path with the GMG preconditioner (8x2x2 -> 4x1x1), FP64
+    or FP32 V-cycle: converges to the oracle's solution."""
     import paper_2505_15535_amd as mfe
     torch, dev = torch_dev
     nx, ny, nz, L, lam = 8, 2, 2, (4.0, 1.0, 1.0), 100.0
@@ -189,8 +221,8 @@ def test_newton_twisted_beam_gmg(torch_dev):
     op.set_constraints(cdofs)
     u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device=dev)
     reps = op.solve_load_path(u, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t), 3,
-                              strategy="t4", preconditioner="gmg", max_newton=30, max_cg=5000,
-                              newton_atol=1e-10, cg_rtol=1e-8)
+                              strategy=strategy, preconditioner="gmg", mg_precision=mg_precision,
+                              max_newton=30, max_cg=5000, newton_atol=1e-10, cg_rtol=1e-8)
     print(reps)
     assert all(r["converged"] for r in reps if not r.get("failed"))
     ug = u.cpu().numpy()
