@@ -167,6 +167,12 @@ def mfe_build_cache(ctx, strategy, stream=None):
     return _check(ctx, _lib.mfe_build_cache(ctx, int(strategy), stream))
 
 
+def mfe_energy(ctx, u_dev_ptr, stream=None) -> float:
+    e = _d()
+    _check(ctx, _lib.mfe_energy(ctx, u_dev_ptr, ctypes.byref(e), stream))
+    return e.value
+
+
 def mfe_build_cache_fp32(ctx, strategy, stream=None):
     return _check(ctx, _lib.mfe_build_cache_fp32(ctx, int(strategy), stream))
 
@@ -318,10 +324,7 @@ class Operator:
 
     def energy(self, u, stream=None):
         """Stored energy at displacement u (float64 device tensor)."""
-        e = _d()
-        _check(self.ctx, _lib.mfe_energy(self.ctx, _dev_f64(u, self.n_dofs, "u"), ctypes.byref(e),
-                                         _stream_handle(stream)))
-        return e.value
+        return mfe_energy(self.ctx, _dev_f64(u, self.n_dofs, "u"), _stream_handle(stream))
 
     def residual(self, u, out=None, stream=None):
         import torch
