@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
-"""Throughput of the matrix-free finite-strain tangent apply on one MI355X.
+"""Throughput of the matrix-free finite-strain tangent apply on one MI355X,
+the mixed-precision apply, and Newton-CG time to a 1e-8 residual.
 
 A step is one application v = K(u) w of the tangent on the 48^3 Q2 box
 (2,738,019 DoF), with the linearisation point and the per-point caches set up
 before the timed region (they are built once per linearisation point; their
 build time is reported separately).  Every strategy is timed; the headline
-`value` is the fastest one.  Prints one JSON line.
+`value` is the fastest one.  Beside it, under "mixed": FP64 and FP32-sweep
+applies on the Q4 24^3 and Q6 12^3 boxes (and the headline box) with the
+error of the FP32 result against the FP64 one; under "newton": the twisted
+beam (64x16x16 Q2, lambda/mu = 100, 90 degrees in 10 load steps) solved to
+||R|| <= 1e-8 with GMG-preconditioned CG, FP64 V-cycle and FP32 V-cycle.
+Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box48_q2]
+                  [--mixed box24_q4,box12_q6] [--no-newton]
 """
 
 from __future__ import annotations
@@ -37,24 +44,26 @@ def sweep_flops_per_q(n: int) -> float:
     return 18.0 * c / n
 
 
-def work_model(strategy: str, degree: int, n_dofs: int, n_q: int, n_vertices: int) -> dict:
+def work_model(strategy: str, degree: int, n_dofs: int, n_q: int, n_vertices: int, elem: int = 8) -> dict:
     """Algorithmic flops and bytes of one apply (each vector read or written
-    once, per-point data streamed once)."""
+    once, per-point data streamed once); elem = bytes of a vector and cache
+    entry (8 for FP64, 4 for the FP32-sweep apply, whose on-the-fly
+    strategies still read the FP64 state, vertices and geometry)."""
     sf = sweep_flops_per_q(degree + 1)
     transform, jxw, geom, kin = 54.0, 9.0, 150.0, 50.0
     pointwise = {"otf": 153.0, "otf_ad": 153.0, "otf_geom": 153.0, "t2": 80.0, "t4": 123.0}[strategy]
     if strategy in ("otf", "otf_ad"):
         fq = 3 * sf + 3 * transform + jxw + geom + kin + pointwise
-        bq, bvec = 0.0, 3 * 8.0 * n_dofs + 24.0 * n_vertices
+        bq, bvec = 0.0, (8.0 + 2 * elem) * n_dofs + 24.0 * n_vertices
     elif strategy == "otf_geom":
         fq = 3 * sf + 3 * transform + jxw + kin + pointwise
-        bq, bvec = 80.0, 3 * 8.0 * n_dofs
+        bq, bvec = 80.0, (8.0 + 2 * elem) * n_dofs
     elif strategy == "t2":
         fq = 2 * sf + 2 * transform + pointwise
-        bq, bvec = 17 * 8.0, 2 * 8.0 * n_dofs
+        bq, bvec = 17.0 * elem, 2.0 * elem * n_dofs
     else:
         fq = 2 * sf + 2 * transform + pointwise
-        bq, bvec = 36 * 8.0, 2 * 8.0 * n_dofs
+        bq, bvec = 36.0 * elem, 2.0 * elem * n_dofs
     flops = fq * n_q
     nbytes = bq * n_q + bvec
     ai = flops / nbytes
@@ -63,10 +72,13 @@ def work_model(strategy: str, degree: int, n_dofs: int, n_q: int, n_vertices: in
             "intensity": ai, "bound": bound}
 
 
-def roofline(model: dict, kernel_ms: float, traffic) -> dict:
+FP32_PEAK_TFLOPS = 157.3      # vector FP32
+
+
+def roofline(model: dict, kernel_ms: float, traffic, alu_peak: float = FP64_PEAK_TFLOPS) -> dict:
     t = kernel_ms * 1e-3
     if model["bound"] == "alu":
-        achieved, peak, unit = model["flops"] / t / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        achieved, peak, unit = model["flops"] / t / 1e12, alu_peak, "TFLOP/s"
     else:
         achieved, peak, unit = model["bytes"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
     return {"bound": model["bound"], "achieved": round(achieved, 3), "peak": peak, "unit": unit,
@@ -124,6 +136,106 @@ def cpu_baseline(cfg, target_s: float = 12.0) -> dict:
             "host_threads": os.cpu_count()}
 
 
+# --------------------------------------------------------------------------- mixed precision
+def time_applies(op, w, v, strategy, precision, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        op.apply(w, out=v, strategy=strategy, precision=precision)
+    op.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(w, out=v, strategy=strategy, precision=precision)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / steps
+    kern_ms, _ = op.apply_kernel_ms()
+    op.set_timing(False)
+    return step_ms, kern_ms
+
+
+def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
+    """FP64 and FP32-sweep applies of one workload; error of the FP32 result
+    against the FP64 one (the FP64 path itself matches the oracle to 1e-12)."""
+    import numpy as np
+    import torch
+
+    import paper_2505_15535_amd as mfe
+    import synthetic
+
+    cfg = synthetic.get_config(name)
+    dev = torch.device("cuda", 0)
+    op = mfe.Operator(cfg.nx, cfg.ny, cfg.nz, cfg.degree, cfg.vertices(), cfg.mu, cfg.lam, device=0)
+    op.set_state(torch.from_numpy(cfg.displacement()).to(dev))
+    w64 = torch.from_numpy(cfg.test_vector(0).astype(np.float32).astype(np.float64)).to(dev)
+    w32 = w64.float()
+    v64, v32 = torch.empty_like(w64), torch.empty_like(w32)
+    nv = (cfg.nx + 1) * (cfg.ny + 1) * (cfg.nz + 1)
+    out = {"n_dofs": op.n_dofs, "degree": cfg.degree, "description": cfg.description}
+    for s in strategies:
+        rec = {}
+        for prec, w, v, elem in (("fp64", w64, v64, 8), ("fp32", w32, v32, 4)):
+            op.build_cache(s, precision=prec)
+            step_ms, kern_ms = time_applies(op, w, v, s, prec, steps, warmup)
+            model = work_model(s, cfg.degree, op.n_dofs, op.n_qpoints, nv, elem)
+            rl = roofline(model, kern_ms, None, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS)
+            rec[prec] = {"ms_per_step": round(step_ms, 5), "kernel_ms": round(kern_ms, 5),
+                         "gdofs": round(op.n_dofs / (step_ms * 1e-3) / 1e9, 4), "roofline": rl}
+        err = float(torch.linalg.norm(v32.double() - v64) / torch.linalg.norm(v64))
+        rec["fp32_rel_err_vs_fp64"] = err
+        rec["speedup_fp32"] = round(rec["fp64"]["ms_per_step"] / rec["fp32"]["ms_per_step"], 3)
+        out[s] = rec
+        print(f"[bench] mixed {name} {s}: fp64 {rec['fp64']['gdofs']:.2f} GDoF/s, fp32 {rec['fp32']['gdofs']:.2f} "
+              f"GDoF/s, rel err {err:.1e}", file=sys.stderr, flush=True)
+    op.close()
+    return out
+
+
+# --------------------------------------------------------------------------- Newton-CG
+NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=8, max_cg=2000, newton_atol=1e-8,
+                   cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0)
+
+
+def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
+    """Twisted beam: left face clamped, right face rotated by `degrees` about
+    the beam axis in `steps` load steps; time to ||R|| <= 1e-8 at the end of
+    the path with the FP64 V-cycle and with the FP32 V-cycle."""
+    import numpy as np
+    import torch
+
+    import paper_2505_15535_amd as mfe
+    import synthetic
+
+    L = (nx / ny, 1.0, 1.0)
+    dev = torch.device("cuda", 0)
+    verts = synthetic.box_vertices(nx, ny, nz, L)
+    cdofs, _ = synthetic.clamp_and_twist(nx, ny, nz, 2, L, 0.0)
+    out = {"workload": f"beam {nx}x{ny}x{nz} Q2, mu=1, lambda={lam}, {degrees:g} deg twist in {steps} load steps",
+           "tolerance": 1e-8, "opts": dict(NEWTON_OPTS)}
+    for prec in ("fp64", "fp32"):
+        op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+        op.set_constraints(cdofs)
+        u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = op.solve_load_path(u, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, np.deg2rad(degrees) * t),
+                                  steps, mg_precision=prec, **NEWTON_OPTS)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        res = float(np.linalg.norm(op.residual(u).cpu().numpy()))
+        out[prec] = {"seconds": round(secs, 3), "final_residual": res,
+                     "load_steps_accepted": sum(1 for r in reps if not r.get("failed")),
+                     "load_steps_rejected": sum(1 for r in reps if r.get("failed")),
+                     "newton_iterations": sum(r["newton_iterations"] for r in reps),
+                     "cg_iterations": sum(r["cg_iterations"] for r in reps),
+                     "pc_fallbacks": sum(r.get("pc_fallbacks", 0) for r in reps)}
+        out["n_dofs"] = op.n_dofs
+        print(f"[bench] newton {prec} V-cycle: {secs:.2f} s, ||R|| {res:.2e}, {out[prec]['newton_iterations']} "
+              f"Newton / {out[prec]['cg_iterations']} CG iterations", file=sys.stderr, flush=True)
+        op.close()
+    out["speedup_fp32"] = round(out["fp64"]["seconds"] / out["fp32"]["seconds"], 3)
+    return out
+
+
 # --------------------------------------------------------------------------- main
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -133,6 +245,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="box48_q2")
     ap.add_argument("--strategies", default=",".join(STRATEGIES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed", default="box24_q4,box12_q6",
+                    help="workloads of the FP64-vs-FP32 apply comparison (the headline one is added)")
+    ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (reference for HBM counters)")
@@ -234,10 +349,16 @@ def main(argv=None):
         "set_state_ms": round(state_ms, 3),
         "strategies": results,
     }
+    op.close()
+    mixed = {}
+    for name in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]:
+        mixed[name] = mixed_leg(name, args.steps, args.warmup)
+    line["mixed"] = mixed
+    if not args.no_newton:
+        line["newton"] = newton_leg()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg)
-    op.close()
     text = json.dumps(line)
     print(text, flush=True)
     if args.out:

@@ -218,6 +218,9 @@ typedef struct mfe_solve_opts {
                              vectors, transfers, smoother and MFE_SF_FP32 level
                              applies) inside the FP64 CG, whose residual, dot
                              products and update stay FP64 (defect correction) */
+    int mg_graph;         /* GMG: 1 = replay each V-cycle from a HIP graph
+                             (captured on a private stream after every level
+                             update; kernel nodes only), 0 = launch eagerly */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64
@@ -263,12 +266,25 @@ int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, co
  * 1D transfer matrices, 8 vectors per level) is built by the first such solve
  * and kept until the mesh, material or constraints change; every solve then
  * interpolates the state to the coarser levels, builds their caches and
- * inverse diagonals, and estimates lambda_max(D^-1 K) per level from 24
+ * inverse diagonals, and estimates lambda_max(D^-1 K) per level from 16
  * Lanczos steps (Jacobi-CG on a fixed random right-hand side); the smoothers
- * use 1.2 times that estimate.  A coarse state with det F <= 0 gives
- * MFE_EJACOBIAN. */
+ * use 1.2 times that estimate.  The V-cycle acts on the free dofs (the
+ * smoother never moves a constrained entry) and the preconditioner is the
+ * identity on the constrained ones.  When a level tangent is not positive
+ * definite (or an interpolated state inverts a cell) the solve uses Jacobi
+ * instead (counted in mfe_solve_report.pc_fallbacks by Newton). */
 int mfe_cg_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* b_dev, double* x_dev,
                  int* iterations_out, double* rel_residual_out, void* stream);
+
+/* The GMG preconditioner on its own, at the current state: mfe_gmg_setup
+ * builds the hierarchy if needed and the level data (states, caches,
+ * diagonals, eigenvalue estimates) as a CG solve with MFE_PC_GMG does;
+ * mfe_gmg_apply then computes z = B r (r_dev, z_dev: device arrays of n_dofs
+ * doubles, not overlapping) with the V-cycle of `opts` (precision, graph).
+ * MFE_ESTATE if the level data were not set up for the current state and
+ * options.  Setup synchronises the stream; apply is asynchronous. */
+int mfe_gmg_setup(mfe_ctx* ctx, const mfe_solve_opts* opts, void* stream);
+int mfe_gmg_apply(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* r_dev, double* z_dev, void* stream);
 
 /* y = a x + b y on device arrays of n_dofs doubles (vector helper for load
  * stepping drivers: predictors, copies with a = 1, b = 0).  Asynchronous. */

@@ -50,7 +50,8 @@ class SolveOpts(ctypes.Structure):
     """struct mfe_solve_opts"""
     _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
                 ("newton_atol", _d), ("cg_rtol", _d), ("mg_levels", _i), ("cheb_degree", _i),
-                ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d), ("mg_precision", _i)]
+                ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d), ("mg_precision", _i),
+                ("mg_graph", _i)]
 
 
 class SolveReport(ctypes.Structure):
@@ -89,6 +90,8 @@ _SIGS = {
     "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
     "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
     "mfe_diagonal": (_i, [_vp, _vp, _vp]),
+    "mfe_gmg_setup": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp]),
+    "mfe_gmg_apply": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp]),
     "mfe_axpby": (_i, [_vp, _d, _vp, _d, _vp, _vp]),
     "mfe_apply_kernel_ms": (_d, [_vp, ctypes.POINTER(_i)]),
 }
@@ -197,6 +200,14 @@ def mfe_newton_solve(ctx, opts: SolveOpts, u_dev_ptr, g_dev_ptr=None, stream=Non
     if rc not in (MFE_OK, MFE_ENOTCONV):
         raise MfeError(rc, mfe_last_error(ctx))
     return rc, rep
+
+
+def mfe_gmg_setup(ctx, opts: SolveOpts, stream=None):
+    return _check(ctx, _lib.mfe_gmg_setup(ctx, ctypes.byref(opts), stream))
+
+
+def mfe_gmg_apply(ctx, opts: SolveOpts, r_dev_ptr, z_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_gmg_apply(ctx, ctypes.byref(opts), r_dev_ptr, z_dev_ptr, stream))
 
 
 def mfe_cg_solve(ctx, opts: SolveOpts, b_dev_ptr, x_dev_ptr, stream=None):
@@ -336,12 +347,12 @@ class Operator:
 
     @staticmethod
     def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
-                   cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=30,
-                   coarse_range=200.0, mg_precision="fp64"):
+                   cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=15,
+                   coarse_range=200.0, mg_precision="fp64", mg_graph=1):
         return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
                          int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol), int(mg_levels),
                          int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range),
-                         PRECISIONS.get(mg_precision, mg_precision))
+                         PRECISIONS.get(mg_precision, mg_precision), int(mg_graph))
 
     def newton_solve(self, u, g=None, stream=None, **opts):
         """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the
@@ -364,6 +375,19 @@ class Operator:
                                    _dev_f64(x, self.n_dofs, "x"), _stream_handle(stream))
         return x, it, rel, STATUS_NAMES.get(rc, rc)
 
+    def gmg_setup(self, stream=None, **opts):
+        """Set up the multigrid level data at the current state (as a GMG CG solve does)."""
+        mfe_gmg_setup(self.ctx, self.solve_opts(preconditioner="gmg", **opts), _stream_handle(stream))
+
+    def gmg_apply(self, r, out=None, stream=None, **opts):
+        """out = B r, one application of the GMG preconditioner (after gmg_setup with the same options)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(r)
+        mfe_gmg_apply(self.ctx, self.solve_opts(preconditioner="gmg", **opts), _dev_f64(r, self.n_dofs, "r"),
+                      _dev_f64(out, self.n_dofs, "out"), _stream_handle(stream))
+        return out
+
     def diagonal(self, out=None, stream=None):
         import torch
         if out is None:
@@ -382,10 +406,11 @@ class Operator:
 
         boundary_values(t) -> (dofs, values): prescribed values at load t on the
         constrained dofs.  Steps of 1/n_steps; a step whose Newton solve fails is
-        retried with half the increment (down to min_fraction) and the increment
-        grows again by 1.25x after each converged step (up to 1/n_steps); each
-        step starts from the linear extrapolation of the two previous converged
-        states.
+        retried with half the increment (down to min_fraction), and later steps
+        stay below 0.9 times the smallest increment that failed; the increment
+        grows again by 1.25x after each converged step (up to those limits);
+        each step starts from the linear extrapolation of the two previous
+        converged states.
         u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
         Returns a list of per-step reports (dicts with t, h and the solver report).
         """
@@ -397,6 +422,7 @@ class Operator:
         g = torch.zeros(n, dtype=torch.float64, device=u.device)
         t, h0 = 0.0, 1.0 / n_steps
         h = h0
+        h_cap = h0
         reports = []
         while t < 1.0 - 1e-12:
             h = min(h, 1.0 - t)
@@ -415,9 +441,10 @@ class Operator:
                 prev_h = h
                 t += h
                 reports.append(dict(t=t, h=h, **rep))
-                h = min(h0, 1.25 * h)
+                h = min(h_cap, 1.25 * h)
             else:
                 reports.append(dict(t=t + h, h=h, failed=True, **rep))
+                h_cap = min(h_cap, 0.9 * h)
                 h *= 0.5
                 if h < min_fraction:
                     raise MfeError(MFE_ENOTCONV, f"load step below {min_fraction} of the path at t = {t}")

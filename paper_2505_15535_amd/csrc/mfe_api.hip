@@ -258,6 +258,16 @@ struct mfe_ctx {
     // geometric multigrid hierarchy (empty until the first GMG solve)
     std::vector<MGLevel> mg;
     int mg_request = -1;  // mg_levels the hierarchy was built for
+    // HIP graph of one preconditioner application
+    hipStream_t mg_stream = nullptr;
+    hipGraphExec_t mg_exec = nullptr;
+    bool mg_graph_valid = false;
+    const double* mg_graph_r = nullptr;
+    double* mg_graph_z = nullptr;
+    int mg_graph_prec = -1;
+    // what the level data were last set up for
+    uint64_t mg_ready_version = 0;
+    int mg_ready_strategy = -1, mg_ready_prec = -1;
     // timing of the apply kernel
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -308,6 +318,9 @@ void mg_free(mfe_ctx* c) {
         if (L.own && L.ctx) mfe_destroy(L.ctx);
     }
     c->mg.clear();
+    if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
+    c->mg_exec = nullptr;
+    c->mg_graph_valid = false;
 }
 
 void free_mesh_data(mfe_ctx* c) {
@@ -391,6 +404,7 @@ void mfe_destroy(mfe_ctx* c) {
     if (c->h_scalars) (void)hipHostFree(c->h_scalars);
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+    if (c->mg_stream) (void)hipStreamDestroy(c->mg_stream);
     delete c;
 }
 
@@ -780,6 +794,7 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
             return fail(c, MFE_EINVAL, "Chebyshev ranges must be finite and > 1");
         if (o->mg_precision != MFE_FP64 && o->mg_precision != MFE_SF_FP32)
             return fail(c, MFE_EINVAL, "mg_precision must be MFE_FP64 or MFE_SF_FP32");
+        if (o->mg_graph != 0 && o->mg_graph != 1) return fail(c, MFE_EINVAL, "mg_graph must be 0 or 1");
     }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
@@ -1035,12 +1050,40 @@ constexpr int precision_of() {
     return std::is_same<T, float>::value ? MFE_SF_FP32 : MFE_FP64;
 }
 
-// v = K_l w on level l in the V-cycle's precision and the solve's strategy
+int apply_mode(int strategy) {
+    switch (strategy) {
+        case MFE_OTF: return mfe::MODE_APPLY_OTF;
+        case MFE_OTF_GEOM: return mfe::MODE_APPLY_OTF_GEOM;
+        case MFE_T2: return mfe::MODE_APPLY_T2;
+        case MFE_T4: return mfe::MODE_APPLY_T4;
+        case MFE_OTF_AD: return mfe::MODE_APPLY_OTF_AD;
+        default: return -1;
+    }
+}
+
+// v += K_l w on level l in the V-cycle's precision and the solve's strategy,
+// a bare kernel launch: v must hold zeros (or a partial sum), w must vanish
+// at the level's constrained dofs, and the rows of v there are not fixed up.
+// The level's caches are built by mg_update.
 template <typename T>
 int level_apply(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* w, T* v, hipStream_t s) {
-    const int rc = mfe_apply_tangent(L.ctx, w, v, o->strategy, precision_of<T>(), s);
-    if (rc != MFE_OK && L.ctx != c) return child_fail(c, L.ctx, rc, "apply");
-    return rc;
+    mfe_ctx* lc = L.ctx;
+    KParams p = base_params(lc);
+    const int slot = cache_slot(o->strategy);
+    if (slot >= 0) {
+        p.cache = lc->d_cache[slot];
+        p.cache32 = lc->d_cache32[slot];
+    }
+    constexpr bool fp32 = std::is_same<T, float>::value;
+    if constexpr (fp32) {
+        p.w32 = w;
+        p.v32 = v;
+    } else {
+        p.w = w;
+        p.v = v;
+    }
+    MFE_HIP(c, mfe::launch_cell_kernel(apply_mode(o->strategy), lc->tab, p, s, fp32));
+    return MFE_OK;
 }
 
 // Largest eigenvalue of the symmetric tridiagonal matrix (a, b) by bisection
@@ -1077,7 +1120,7 @@ double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) 
 // whose largest eigenvalue approaches lambda_max from below.
 int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
     const int64_t n = L.ctx->n_dofs;
-    const int m = (int)std::min<int64_t>(24, n);
+    const int m = (int)std::min<int64_t>(16, n);
     double* x = L.v64.x;
     double* r = L.v64.b;
     double* z = L.v64.tmp1;
@@ -1165,14 +1208,27 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
         rc = lanczos_lmax(c, L, s, lam);
         if (rc != MFE_OK) return rc;
         L.lmax = lam;
-        if (fp32) MFE_HIP(c, mfe::launch_convert(L.v64.dinv, L.v32.dinv, lc->n_dofs, s));
+        // the V-cycle works on the free dofs: the smoother never moves a
+        // constrained entry, and its operator-output buffer starts cleared
+        if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.v64.dinv, s));
+        MFE_HIP(c, mfe::launch_fill(L.v64.r, lc->n_dofs, 0.0, s));
+        if (fp32) {
+            MFE_HIP(c, mfe::launch_convert(L.v64.dinv, L.v32.dinv, lc->n_dofs, s));
+            MFE_HIP(c, mfe::launch_fill(L.v32.r, lc->n_dofs, 0.0f, s));
+        }
     }
+    c->mg_graph_valid = false;  // smoother coefficients changed
+    c->mg_ready_version = c->state_version;
+    c->mg_ready_strategy = o->strategy;
+    c->mg_ready_prec = o->mg_precision;
     return MFE_OK;
 }
 
 // x = x + p(D^-1 K) D^-1 (b - K x): `degree` Chebyshev-Jacobi steps on
 // [lmax / range, lmax] with lmax 1.2 times the estimate (x = 0 on entry when
-// zero_start, which saves one operator application).
+// zero_start, which saves one operator application).  On the free dofs only:
+// dinv is 0 at constrained dofs, so x stays 0 there.  The operator output V.r
+// is zero on entry and on exit (each step clears it after use).
 template <typename T>
 int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* b, T* x, int degree, double range,
               bool zero_start, hipStream_t s) {
@@ -1184,24 +1240,24 @@ int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* b, T* x,
     int rc;
     if (zero_start) {
         MFE_HIP(c, mfe::launch_fill(x, n, T(0), s));
-        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(nullptr), V.dinv, T(0), T(1.0 / theta), n, s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<T*>(nullptr), V.dinv, T(0), T(1.0 / theta), n, s));
     } else {
         rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
         if (rc != MFE_OK) return rc;
-        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(V.r), V.dinv, T(0), T(1.0 / theta), n, s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, V.r, V.dinv, T(0), T(1.0 / theta), n, s));
     }
     for (int k = 1; k < degree; ++k) {
         rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
         if (rc != MFE_OK) return rc;
         const double rho_new = 1.0 / (2.0 * sigma - rho);
-        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<const T*>(V.r), V.dinv, T(rho_new * rho),
-                                    T(2.0 * rho_new / delta), n, s));
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, V.r, V.dinv, T(rho_new * rho), T(2.0 * rho_new / delta), n, s));
         rho = rho_new;
     }
     return MFE_OK;
 }
 
-// one V-cycle x = V_l b on level l (x need not be initialised)
+// one V-cycle x = V_l b on the free dofs of level l (x need not be
+// initialised; b is not read at constrained dofs; x is 0 there on exit)
 template <typename T>
 int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipStream_t s) {
     MGLevel& L = c->mg[l];
@@ -1211,6 +1267,7 @@ int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipS
     int rc = chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, true, s);
     if (rc != MFE_OK) return rc;
     const int64_t n = lc->n_dofs;
+    // residual b - K x on the free dofs
     rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
     if (rc != MFE_OK) return rc;
     MFE_HIP(c, mfe::launch_axpby(T(1), b, T(-1), V.r, n, s));
@@ -1219,23 +1276,23 @@ int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipS
     MGVec<T>& CV = C.vecs(static_cast<T*>(nullptr));
     rc = tensor_apply(c, L.R, static_cast<const T*>(V.r), V.tmp1, V.tmp2, CV.b, s);
     if (rc != MFE_OK) return rc;
-    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, T(0), CV.b, s));
     rc = vcycle(c, o, l + 1, static_cast<const T*>(CV.b), CV.x, s);
     if (rc != MFE_OK) return rc;
-    if (C.ctx->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(C.ctx->d_cidx, C.ctx->n_con, T(0), CV.x, s));
     rc = tensor_apply(c, L.P, static_cast<const T*>(CV.x), V.tmp1, V.tmp2, V.r, s);  // prolongated correction
     if (rc != MFE_OK) return rc;
     if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, T(0), V.r, s));
-    MFE_HIP(c, mfe::launch_axpby(T(1), static_cast<const T*>(V.r), T(1), x, n, s));
+    MFE_HIP(c, mfe::launch_add_clear(x, V.r, n, s));  // x += correction, V.r cleared again
     return chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, false, s);
 }
 
-// z = V r with the GMG hierarchy of c (FP64 or FP32 V-cycle), then r.z
-int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s, double& rz) {
+// The whole preconditioner application z = B r as one kernel sequence (no
+// host synchronisation): B is the V-cycle on the free dofs and the identity
+// on the constrained ones (exact for the identity rows of K).
+int gmg_body(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s) {
+    MGLevel& L = c->mg[0];
+    const int64_t n = c->n_dofs;
     int rc;
     if (o->mg_precision == MFE_SF_FP32) {
-        MGLevel& L = c->mg[0];
-        const int64_t n = c->n_dofs;
         MFE_HIP(c, mfe::launch_convert(r, L.v32.b, n, s));
         rc = vcycle(c, o, 0, static_cast<const float*>(L.v32.b), L.v32.x, s);
         if (rc != MFE_OK) return rc;
@@ -1244,6 +1301,49 @@ int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, doubl
         rc = vcycle(c, o, 0, r, z, s);
         if (rc != MFE_OK) return rc;
     }
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, r, z, s));
+    return MFE_OK;
+}
+
+// z = B r, replayed from a HIP graph of gmg_body when opts->mg_graph is set
+// (captured once per hierarchy update and (r, z, precision)), else launched
+// kernel by kernel.  The graph holds kernel nodes only.
+int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s) {
+    if (!o->mg_graph) return gmg_body(c, o, r, z, s);
+    if (!c->mg_graph_valid || c->mg_graph_r != r || c->mg_graph_z != z || c->mg_graph_prec != o->mg_precision) {
+        if (c->mg_exec) {
+            (void)hipGraphExecDestroy(c->mg_exec);
+            c->mg_exec = nullptr;
+        }
+        if (!c->mg_stream) MFE_HIP(c, hipStreamCreateWithFlags(&c->mg_stream, hipStreamNonBlocking));
+        MFE_HIP(c, hipStreamBeginCapture(c->mg_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = gmg_body(c, o, r, z, c->mg_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->mg_stream, &graph);
+        if (rc != MFE_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        const hipError_t ei = hipGraphInstantiate(&c->mg_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            c->mg_exec = nullptr;
+            return hip_fail(c, ei, "hipGraphInstantiate");
+        }
+        c->mg_graph_valid = true;
+        c->mg_graph_r = r;
+        c->mg_graph_z = z;
+        c->mg_graph_prec = o->mg_precision;
+    }
+    MFE_HIP(c, hipGraphLaunch(c->mg_exec, s));
+    return MFE_OK;
+}
+
+// z = B r with the GMG hierarchy of c, then r.z (must be positive)
+int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s, double& rz) {
+    int rc = gmg_apply(c, o, r, z, s);
+    if (rc != MFE_OK) return rc;
     double unused;
     rc = dot2(c, r, z, nullptr, nullptr, s, rz, unused);
     if (rc != MFE_OK) return rc;
@@ -1363,6 +1463,60 @@ int mfe_diagonal(mfe_ctx* c, double* d, void* stream) {
     int rc = ensure_work(c);
     if (rc != MFE_OK) return rc;
     return diagonal_into(c, d, static_cast<hipStream_t>(stream));
+}
+
+// shared checks of the standalone GMG entry points; o2 gets the options with
+// the preconditioner set to GMG
+static int gmg_entry(mfe_ctx* c, const mfe_solve_opts* o, mfe_solve_opts& o2) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!o) return fail(c, MFE_EINVAL, "null options");
+    o2 = *o;
+    o2.preconditioner = MFE_PC_GMG;
+    int rc = check_opts(c, &o2);
+    if (rc != MFE_OK) return rc;
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    return ensure_work(c);
+}
+
+int mfe_gmg_setup(mfe_ctx* c, const mfe_solve_opts* o, void* stream) {
+    mfe_solve_opts o2;
+    int rc = gmg_entry(c, o, o2);
+    if (rc != MFE_OK) return rc;
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (o2.strategy != MFE_OTF && o2.strategy != MFE_OTF_AD) {
+        const int slot = cache_slot(o2.strategy);
+        if (!c->cache_valid[slot] || (slot > 0 && c->cache_version[slot] != c->state_version)) {
+            rc = mfe_build_cache(c, o2.strategy, s);
+            if (rc != MFE_OK) return rc;
+        }
+    }
+    rc = mg_build(c, o2.mg_levels);
+    if (rc != MFE_OK) return rc;
+    return mg_update(c, &o2, s);
+}
+
+int mfe_gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, void* stream) {
+    mfe_solve_opts o2;
+    int rc = gmg_entry(c, o, o2);
+    if (rc != MFE_OK) return rc;
+    if (!r || !z) return fail(c, MFE_EINVAL, "null vector");
+    if (overlaps(r, z, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "r and z overlap");
+    if (c->mg.empty() || c->mg_request != o2.mg_levels || c->mg_ready_version != c->state_version ||
+        c->mg_ready_strategy != o2.strategy || c->mg_ready_prec != o2.mg_precision)
+        return fail(c, MFE_ESTATE, "multigrid level data not set up for this state and these options");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n_dofs;
+    double* rw = c->d_work;      // the CG residual and preconditioned residual slots:
+    double* zw = c->d_work + n;  // the same buffers as inside CG, so one graph serves both
+    MFE_HIP(c, mfe::launch_copy(r, rw, n, s));
+    rc = gmg_apply(c, &o2, rw, zw, s);
+    if (rc != MFE_OK) return rc;
+    MFE_HIP(c, mfe::launch_copy(static_cast<const double*>(zw), z, n, s));
+    return MFE_OK;
 }
 
 int mfe_cg_solve(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, int* iterations_out,

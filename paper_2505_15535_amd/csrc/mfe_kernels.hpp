@@ -106,11 +106,17 @@ hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* v
 hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const float* vals, int axis, int nx_out,
                            int ny_out, int nz_out, int nx_in, int ny_in, const float* in, float* out,
                            hipStream_t s);
-// d = c1 d + c2 dinv .* (b - Ax);  x += d  (Ax null: b; d is not read when c1 = 0)
-hipError_t launch_cheb(double* d, double* x, const double* b, const double* Ax, const double* dinv, double c1,
+// d = c1 d + c2 dinv .* (b - Ax);  x += d;  Ax = 0  (Ax null: b; d is not read when c1 = 0)
+hipError_t launch_cheb(double* d, double* x, const double* b, double* Ax, const double* dinv, double c1,
                        double c2, int64_t n, hipStream_t s);
-hipError_t launch_cheb(float* d, float* x, const float* b, const float* Ax, const float* dinv, float c1, float c2,
+hipError_t launch_cheb(float* d, float* x, const float* b, float* Ax, const float* dinv, float c1, float c2,
                        int64_t n, hipStream_t s);
+// x += y;  y = 0
+hipError_t launch_add_clear(double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_add_clear(float* x, float* y, int64_t n, hipStream_t s);
+// y = x
+hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_copy(const float* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_axpby(float a, const float* x, float b, float* y, int64_t n, hipStream_t s);
 hipError_t launch_convert(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_convert(const float* src, double* dst, int64_t n, hipStream_t s);

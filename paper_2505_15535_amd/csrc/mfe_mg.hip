@@ -37,19 +37,41 @@ __global__ void axis_csr_kernel(const int* __restrict__ rowptr, const int* __res
 }
 
 // Chebyshev step with the residual formed on the fly:
-//   d = c1 d + c2 dinv .* (b - Ax);  x += d
-// (Ax null: residual b; c1 = 0: d is not read).
+//   d = c1 d + c2 dinv .* (b - Ax);  x += d;  Ax = 0
+// (Ax null: residual b; c1 = 0: d is not read).  Clearing Ax leaves the
+// buffer ready for the next operator application, which accumulates.
 template <typename T>
-__global__ void cheb_kernel(T* __restrict__ d, T* __restrict__ x, const T* __restrict__ b,
-                            const T* __restrict__ Ax, const T* __restrict__ dinv, T c1, T c2, int64_t n) {
+__global__ void cheb_kernel(T* __restrict__ d, T* __restrict__ x, const T* __restrict__ b, T* __restrict__ Ax,
+                            const T* __restrict__ dinv, T c1, T c2, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const T r = Ax ? b[i] - Ax[i] : b[i];
+        T r = b[i];
+        if (Ax) {
+            r -= Ax[i];
+            Ax[i] = T(0);
+        }
         const T step = c2 * dinv[i] * r;
         const T di = c1 == T(0) ? step : fma(c1, d[i], step);
         d[i] = di;
         x[i] += di;
     }
+}
+
+// x += y;  y = 0
+template <typename T>
+__global__ void add_clear_kernel(T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        x[i] += y[i];
+        y[i] = T(0);
+    }
+}
+
+// y = x (plain copy)
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = x[i];
 }
 
 // y = a x + b y
@@ -90,19 +112,34 @@ hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const float* va
 }
 
 template <typename T>
-static hipError_t cheb_t(T* d, T* x, const T* b, const T* Ax, const T* dinv, T c1, T c2, int64_t n,
-                         hipStream_t s) {
+static hipError_t cheb_t(T* d, T* x, const T* b, T* Ax, const T* dinv, T c1, T c2, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(cheb_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, d, x, b, Ax, dinv, c1, c2, n);
     return hipGetLastError();
 }
-hipError_t launch_cheb(double* d, double* x, const double* b, const double* Ax, const double* dinv, double c1,
+hipError_t launch_cheb(double* d, double* x, const double* b, double* Ax, const double* dinv, double c1,
                        double c2, int64_t n, hipStream_t s) {
     return cheb_t(d, x, b, Ax, dinv, c1, c2, n, s);
 }
-hipError_t launch_cheb(float* d, float* x, const float* b, const float* Ax, const float* dinv, float c1, float c2,
+hipError_t launch_cheb(float* d, float* x, const float* b, float* Ax, const float* dinv, float c1, float c2,
                        int64_t n, hipStream_t s) {
     return cheb_t(d, x, b, Ax, dinv, c1, c2, n, s);
 }
+
+template <typename T>
+static hipError_t add_clear_t(T* x, T* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(add_clear_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_add_clear(double* x, double* y, int64_t n, hipStream_t s) { return add_clear_t(x, y, n, s); }
+hipError_t launch_add_clear(float* x, float* y, int64_t n, hipStream_t s) { return add_clear_t(x, y, n, s); }
+
+template <typename T>
+static hipError_t copy_t(const T* x, T* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t s) { return copy_t(x, y, n, s); }
+hipError_t launch_copy(const float* x, float* y, int64_t n, hipStream_t s) { return copy_t(x, y, n, s); }
 
 hipError_t launch_axpby(float a, const float* x, float b, float* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(axpby_t_kernel<float>, dim3(grid_of(n)), dim3(256), 0, s, a, x, b, y, n);

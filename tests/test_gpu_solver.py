@@ -136,6 +136,55 @@ def test_gmg_fp32_vcycle_defect_correction(torch_dev):
         assert it <= 1.25 * res["fp64", "t2"][1] + 2, k
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_gmg_preconditioner_graph_and_symmetry(torch_dev, prec, tol):
+    """One V-cycle replayed from the HIP graph equals the eagerly launched one
+    on every replay (with other GPU work in between), B is symmetric and
+    positive, and it is the identity on the constrained dofs."""
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz, L = 16, 4, 4, (4.0, 1.0, 1.0)
+    verts = synthetic.box_vertices(nx, ny, nz, L, jitter=0.15, rng=synthetic.rng_for(92, 0))
+    cdofs, vals = synthetic.clamp_and_twist(nx, ny, nz, 2, L, np.deg2rad(5.0))
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, 10.0, device=0)
+    op.set_constraints(cdofs)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
+    u[torch.from_numpy(cdofs).to(dev)] = _to(torch_dev, vals)
+    op.set_state(u)
+    op.build_cache("t2")
+    R = [_to(torch_dev, r) for r in synthetic.random_vectors(op.n_dofs, 2, synthetic.rng_for(92, 2))]
+    opts = dict(strategy="t2", mg_precision=prec)
+    with pytest.raises(mfe.MfeError) as e:
+        op.gmg_apply(R[0], **opts)          # level data not set up yet
+    assert e.value.code == mfe.MFE_ESTATE
+    op.gmg_setup(**opts)
+    eager = [op.gmg_apply(r, mg_graph=0, **opts).clone() for r in R]
+    for rep in range(3):
+        for k, r in enumerate(R):
+            zg = op.gmg_apply(r, mg_graph=1, **opts)
+            rel = float(torch.linalg.norm(zg - eager[k]) / torch.linalg.norm(eager[k]))
+            assert rel <= tol, (rep, k, rel)
+        op.apply(R[0], strategy="t2")       # unrelated eager work between replays
+        torch.cuda.synchronize()
+    z0, z1 = eager
+    a, b = float(torch.dot(R[1], z0)), float(torch.dot(R[0], z1))
+    assert abs(a - b) <= 10 * tol * max(abs(a), abs(b)) + 1e-14
+    assert float(torch.dot(R[0], z0)) > 0.0 and float(torch.dot(R[1], z1)) > 0.0
+    ci = torch.from_numpy(cdofs).to(dev)
+    assert torch.equal(z0[ci], R[0][ci])
+    # the FP32 V-cycle really runs in FP32: it differs from the FP64 one at the
+    # level of FP32 rounding, not more
+    other = "fp64" if prec == "fp32" else "fp32"
+    op.gmg_setup(strategy="t2", mg_precision=other)
+    zo = op.gmg_apply(R[0], strategy="t2", mg_precision=other)
+    d = float(torch.linalg.norm(zo - z0) / torch.linalg.norm(z0))
+    assert 1e-10 < d < 1e-4, d
+    op.set_state(0.5 * u)
+    with pytest.raises(mfe.MfeError) as e:
+        op.gmg_apply(R[0], **opts)          # stale after a new state
+    assert e.value.code == mfe.MFE_ESTATE
+
+
 def test_gmg_per_cell_material_and_options(torch_dev):
     """Per-cell (mu, lambda) averaged onto the coarse levels; option checks."""
     import paper_2505_15535_amd as mfe
@@ -164,7 +213,7 @@ def test_gmg_per_cell_material_and_options(torch_dev):
     assert status == "MFE_OK" and it < 60
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
     for bad in ({"cheb_degree": 0}, {"cheb_range": 1.0}, {"coarse_degree": 0}, {"coarse_range": float("nan")},
-                {"mg_levels": -1}, {"mg_precision": 2}):
+                {"mg_levels": -1}, {"mg_precision": 2}, {"mg_graph": 2}):
         with pytest.raises(mfe.MfeError, match="MFE_EINVAL"):
             op.cg_solve(_to(torch_dev, b), preconditioner="gmg", **bad)
 
