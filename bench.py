@@ -236,6 +236,54 @@ def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
     return out
 
 
+# --------------------------------------------------------------------------- learned correction
+def learned_leg(nx=64, ny=16, nz=16, epochs=20, variant="relu") -> dict:
+    """Train the learned smoother correction on residuals from load paths with
+    other twist angles and lambda/mu (30 deg / 30, 80 deg / 300, 120 deg / 10),
+    then solve the held-out twisted beam (90 deg, lambda = 100, 10 steps) with
+    GMG and with GMG plus the correction; CG iterations and time for both."""
+    import numpy as np
+    import torch
+
+    from paper_2505_15535_amd import learned
+
+    t0 = time.perf_counter()
+    data = learned.generate([(30.0, 30.0), (80.0, 300.0), (120.0, 10.0)], nx=nx, ny=ny, nz=nz, steps=6,
+                            states_per_path=4, n_loads=2, seed=1)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    netw, hist = learned.train(data, nx=nx, ny=ny, nz=nz, epochs=epochs, lr=1e-3, seed=0, variant=variant)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out = {"workload": f"held-out beam {nx}x{ny}x{nz} Q2, lambda=100, 90 deg in 10 steps",
+           "training": {"paths": "30deg/lambda30, 80deg/lambda300, 120deg/lambda10", "variant": variant,
+                        "samples": sum(len(s.residuals) for _, ss in data for s in ss),
+                        "patches_per_sample": (nx // 4) * (ny // 4) * (nz // 4), "epochs": epochs,
+                        "generate_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                        "mean_energy_first_last": [hist[0], hist[-1]]}}
+    op, bv, cd = learned.beam(nx, ny, nz, 100.0)
+    op.set_network(netw.params(), variant)
+    for pc in ("gmg", "gmg_net"):
+        u = torch.zeros(op.n_dofs, dtype=torch.float64, device=op.device)
+        op.set_network(netw.params(), variant)  # clears a fallback of an earlier solve
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = op.solve_load_path(u, bv(90.0), 10, **dict(NEWTON_OPTS, preconditioner=pc))
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[pc] = {"seconds": round(secs, 3),
+                   "final_residual": float(np.linalg.norm(op.residual(u).cpu().numpy())),
+                   "newton_iterations": sum(r["newton_iterations"] for r in reps),
+                   "cg_iterations": sum(r["cg_iterations"] for r in reps),
+                   "net_fallbacks": sum(r.get("net_fallbacks", 0) for r in reps)}
+        print(f"[bench] learned {pc}: {secs:.2f} s, {out[pc]['cg_iterations']} CG iterations, "
+              f"{out[pc]['net_fallbacks']} fallbacks", file=sys.stderr, flush=True)
+    op.close()
+    out["cg_iteration_ratio"] = round(out["gmg_net"]["cg_iterations"] / max(out["gmg"]["cg_iterations"], 1), 3)
+    out["time_ratio"] = round(out["gmg_net"]["seconds"] / out["gmg"]["seconds"], 3)
+    return out
+
+
 # --------------------------------------------------------------------------- main
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -248,8 +296,8 @@ def main(argv=None):
     ap.add_argument("--mixed", default="box24_q4,box12_q6",
                     help="workloads of the FP64-vs-FP32 apply comparison (the headline one is added)")
     ap.add_argument("--no-newton", action="store_true")
-    ap.add_argument("--legs", default="apply,mixed,newton",
-                    help="subset of apply,mixed,newton to run (profiling runs; the default runs all)")
+    ap.add_argument("--legs", default="apply,mixed,newton,learned",
+                    help="subset of apply,mixed,newton,learned to run (profiling runs; the default runs all)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (reference for HBM counters)")
@@ -338,6 +386,8 @@ def main(argv=None):
                              for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
         if "newton" in legs and not args.no_newton:
             line["newton"] = newton_leg()
+        if "learned" in legs:
+            line["learned"] = learned_leg()
         print(json.dumps(line), flush=True)
         return 0
     best = max(results, key=lambda k: results[k]["gdofs"])
@@ -368,6 +418,8 @@ def main(argv=None):
                          for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
     if "newton" in legs and not args.no_newton:
         line["newton"] = newton_leg()
+    if "learned" in legs:
+        line["learned"] = learned_leg()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg)

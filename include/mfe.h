@@ -193,12 +193,21 @@ int mfe_energy(mfe_ctx* ctx, const double* u_dev, double* energy_host, void* str
 typedef enum mfe_preconditioner {
     MFE_PC_NONE = 0,      /* plain CG */
     MFE_PC_JACOBI = 1,    /* inverse of |diagonal of K(u)| (matrix-free diagonal) */
-    MFE_PC_GMG = 2        /* one geometric multigrid V-cycle (Sec. 2.3): nested
+    MFE_PC_GMG = 2,       /* one geometric multigrid V-cycle (Sec. 2.3): nested
                              boxes, each coarser one halving the cell counts
                              while all three are even; level operators K(u_l)
                              at the nodal interpolant u_l of the state;
                              Chebyshev-Jacobi pre- and post-smoothing;
                              Chebyshev-Jacobi on the coarsest level */
+    MFE_PC_GMG_NET = 3    /* the V-cycle z = V r plus alpha N, N the learned
+                             correction (mfe_set_network) of the residual
+                             r1 = r - K z, alpha = N.r1 / N.K N (the step that
+                             minimises the error's energy norm along N; no step
+                             when either dot is <= 0), inside flexible CG; the
+                             correction is dropped when the residual stagnates
+                             (< 10% reduction over 3 iterations) or r.Br <= 0,
+                             for the rest of that solve and for later solves on
+                             the context until mfe_set_network is called */
 } mfe_preconditioner;
 
 typedef struct mfe_solve_opts {
@@ -231,6 +240,8 @@ typedef struct mfe_solve_report {
     int backtracks;            /* step halvings (line search and boundary steps) */
     int pc_fallbacks;          /* CG solves in which GMG was replaced by Jacobi
                                   (a level tangent was not positive definite) */
+    int net_fallbacks;         /* CG solves in which the learned correction was
+                                  dropped (stagnation or r.Br <= 0) */
     double initial_residual;   /* ||R(u_in)||_2 */
     double final_residual;     /* ||R(u_out)||_2 */
     double residual_history[MFE_HISTORY];  /* ||R|| before each correction, then the final one */
@@ -301,6 +312,81 @@ int mfe_diagonal(mfe_ctx* ctx, double* d_dev, void* stream);
  * mfe_set_timing(ctx, 1) and costs two event records per apply. */
 int mfe_set_timing(mfe_ctx* ctx, int enabled);
 double mfe_apply_kernel_ms(mfe_ctx* ctx, int* count_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother correction (the method's "learned parts" growth direction):
+ * a 3D convolutional network on patches of 4x4x4 Q2 cells (9x9x9 nodes;
+ * patch (px,py,pz) holds nodes (8px+i, 8py+j, 8pz+k), i,j,k = 0..8, so
+ * neighbouring patches share face nodes).  Input channels per node: the
+ * residual (3 components) divided by the patch RMS s_p of the residual, and
+ * I1 - 3, I2 - 3, J - 1 of C = F^T F (F at the centres of the node's cells,
+ * averaged); output: 3 channels, the correction divided by s_p.  Layers:
+ * conv 6->32 + ReLU, conv 32->32 + ReLU, conv 32->3, 3x3x3 kernels, zero
+ * padding.  Parameters (FP32, MFE_NET_PARAMS): per layer W[co][ci][tap]
+ * (tap = a + 3b + 9c for the offset (a-1, b-1, c-1)) then bias[co].
+ * Activations are [patch][channel][729] floats with node v = i + 9j + 81k.
+ * All of it FP32; every pointer below is a device pointer unless named _host.
+ * ------------------------------------------------------------------------- */
+#define MFE_NET_PARAMS 35491
+/* Network variants: MFE_NET_RELU as above; MFE_NET_LINEAR drops the ReLUs,
+ * the biases, the patch scaling (s_p = 1) and the invariant channels (0), so
+ * that the correction is a fixed linear map of the residual and the
+ * preconditioner a fixed linear operator within a solve (its step alpha is
+ * chosen at a solve's first application and then kept). */
+#define MFE_NET_RELU 0
+#define MFE_NET_LINEAR 1
+
+/* Copy the network parameters (host, MFE_NET_PARAMS floats) and its variant
+ * into the context for MFE_PC_GMG_NET; NULL clears them.  MFE_EINVAL for
+ * non-finite values or an unknown variant.  Synchronous. */
+int mfe_set_network(mfe_ctx* ctx, const float* params_host, int variant);
+
+/* Number of patches of the mesh (0 unless degree 2 with nx, ny, nz
+ * divisible by 4). */
+int64_t mfe_patch_count(const mfe_ctx* ctx);
+
+/* feat[P][6][729] and scale[P] (s_p) from a residual r (n_dofs doubles) at
+ * the current state, for the network `variant`.  MFE_ESTATE without a state, MFE_EUNSUPPORTED without
+ * patches.  Asynchronous. */
+int mfe_patch_features(mfe_ctx* ctx, const double* r_dev, float* feat_dev, float* scale_dev, int variant,
+                       void* stream);
+
+/* t[P][3][729] = e at the patch nodes / s_p (0 where s_p = 0). */
+int mfe_patch_targets(mfe_ctx* ctx, const double* e_dev, const float* scale_dev, float* t_dev, void* stream);
+
+/* z += alpha * (patch outputs y[P][3][729] times s_p, averaged over the
+ * patches that hold each node).  Constrained dofs are not special here. */
+int mfe_patch_scatter(mfe_ctx* ctx, const float* y_dev, const float* scale_dev, double alpha, double* z_dev,
+                      void* stream);
+
+/* Adjoint of mfe_patch_scatter: dy[P][3][729] = alpha * s_p * g(node) / (number
+ * of patches holding the node), i.e. d L / d y for d L / d z = g (g: n_dofs
+ * doubles).  Used to train the network on a loss of the assembled z. */
+int mfe_patch_adjoint(mfe_ctx* ctx, const double* g_dev, const float* scale_dev, double alpha, float* dy_dev,
+                      void* stream);
+
+/* y[P][3][729] = network(x[P][6][729]); act[2][P][32][729] receives the
+ * hidden activations (needed by the backward pass).  Asynchronous. */
+int mfe_net_forward(const float* params_dev, const float* x_dev, int n_patches, int variant, float* act_dev,
+                    float* y_dev, void* stream);
+
+/* grad[MFE_NET_PARAMS] = d loss / d params given dy = d loss / d y, with x
+ * and act from the forward pass; work: [2][P][32][729] floats of scratch.
+ * Weight gradients are per-workgroup sums in a fixed order (deterministic).
+ * Asynchronous. */
+int mfe_net_backward(const float* params_dev, const float* x_dev, const float* act_dev, const float* dy_dev,
+                     int n_patches, int variant, float* work_dev, float* grad_dev, void* stream);
+
+/* *loss_host = mean of (y - t)^2 over n entries (accumulated in FP64); dy
+ * (may be NULL) = 2 (y - t) / n.  scratch: 1025 doubles.  Synchronises. */
+int mfe_net_loss(const float* y_dev, const float* t_dev, int64_t n, float* dy_dev, double* scratch_dev,
+                 double* loss_host, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected for
+ * step >= 1) on MFE_NET_PARAMS parameters; m, v: moment buffers (start at 0).
+ * Asynchronous. */
+int mfe_net_adam(float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int step, float lr,
+                 void* stream);
 
 #ifdef __cplusplus
 }

@@ -25,10 +25,12 @@ material  energy, first Piola-Kirchhoff stress, explicit tangent tensor
 fem       state, residual, energy, assembled tangent, naive apply
 linelast  textbook small-strain stiffness B^T D B (pin for the u = 0 limit)
 solver    Newton on the weak form with assembled tangent and direct solves
+net       the learned smoother's convolutional network: forward, loss,
+          parameter gradients, Adam step, patch node map
 
 Every function is float64 unless it is fed complex128 input for the
 complex-step pins, in which case it works in complex128 throughout.
 """
 
-from . import basis, mesh, material, fem, linelast, solver  # noqa: F401
+from . import basis, mesh, material, fem, linelast, solver, net  # noqa: F401
 from .mesh import BoxMesh  # noqa: F401

@@ -30,8 +30,11 @@ STRATEGIES = {"otf": MFE_OTF, "otf_geom": MFE_OTF_GEOM, "t2": MFE_T2, "t4": MFE_
 MFE_FP64, MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": MFE_FP64, "fp32": MFE_SF_FP32, "bf16": MFE_SF_BF16, "bf16x3": MFE_SF_BF16X3}
 # preconditioners of the Newton-CG solver
-MFE_PC_NONE, MFE_PC_JACOBI, MFE_PC_GMG = 0, 1, 2
-PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI, "gmg": MFE_PC_GMG}
+MFE_PC_NONE, MFE_PC_JACOBI, MFE_PC_GMG, MFE_PC_GMG_NET = 0, 1, 2, 3
+PRECONDITIONERS = {"none": MFE_PC_NONE, "jacobi": MFE_PC_JACOBI, "gmg": MFE_PC_GMG, "gmg_net": MFE_PC_GMG_NET}
+MFE_NET_PARAMS = 35491
+MFE_NET_RELU, MFE_NET_LINEAR = 0, 1
+NET_VARIANTS = {"relu": MFE_NET_RELU, "linear": MFE_NET_LINEAR}
 MFE_HISTORY = 64
 
 if not os.path.exists(LIB_PATH):
@@ -57,14 +60,14 @@ class SolveOpts(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     """struct mfe_solve_report"""
     _fields_ = [("converged", _i), ("newton_iterations", _i), ("cg_iterations", _i), ("backtracks", _i),
-                ("pc_fallbacks", _i), ("initial_residual", _d), ("final_residual", _d),
+                ("pc_fallbacks", _i), ("net_fallbacks", _i), ("initial_residual", _d), ("final_residual", _d),
                 ("residual_history", _d * MFE_HISTORY)]
 
     def as_dict(self):
         n = min(self.newton_iterations + 1, MFE_HISTORY)
         return {"converged": bool(self.converged), "newton_iterations": self.newton_iterations,
                 "cg_iterations": self.cg_iterations, "backtracks": self.backtracks,
-                "pc_fallbacks": self.pc_fallbacks,
+                "pc_fallbacks": self.pc_fallbacks, "net_fallbacks": self.net_fallbacks,
                 "initial_residual": self.initial_residual,
                 "final_residual": self.final_residual, "residual_history": list(self.residual_history[:n])}
 
@@ -91,6 +94,16 @@ _SIGS = {
     "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
     "mfe_diagonal": (_i, [_vp, _vp, _vp]),
     "mfe_gmg_setup": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp]),
+    "mfe_set_network": (_i, [_vp, _vp, _i]),
+    "mfe_patch_count": (_i64, [_vp]),
+    "mfe_patch_features": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
+    "mfe_patch_targets": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "mfe_patch_scatter": (_i, [_vp, _vp, _vp, _d, _vp, _vp]),
+    "mfe_patch_adjoint": (_i, [_vp, _vp, _vp, _d, _vp, _vp]),
+    "mfe_net_forward": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp]),
+    "mfe_net_backward": (_i, [_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp]),
+    "mfe_net_loss": (_i, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "mfe_net_adam": (_i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     "mfe_gmg_apply": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp]),
     "mfe_axpby": (_i, [_vp, _d, _vp, _d, _vp, _vp]),
     "mfe_apply_kernel_ms": (_d, [_vp, ctypes.POINTER(_i)]),
@@ -208,6 +221,59 @@ def mfe_gmg_setup(ctx, opts: SolveOpts, stream=None):
 
 def mfe_gmg_apply(ctx, opts: SolveOpts, r_dev_ptr, z_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_gmg_apply(ctx, ctypes.byref(opts), r_dev_ptr, z_dev_ptr, stream))
+
+
+def mfe_set_network(ctx, params_host_ptr, variant=MFE_NET_RELU):
+    return _check(ctx, _lib.mfe_set_network(ctx, params_host_ptr, int(variant)))
+
+
+def mfe_patch_count(ctx) -> int:
+    return int(_lib.mfe_patch_count(ctx))
+
+
+def mfe_patch_features(ctx, r_dev_ptr, feat_dev_ptr, scale_dev_ptr, variant=MFE_NET_RELU, stream=None):
+    return _check(ctx, _lib.mfe_patch_features(ctx, r_dev_ptr, feat_dev_ptr, scale_dev_ptr, int(variant), stream))
+
+
+def mfe_patch_targets(ctx, e_dev_ptr, scale_dev_ptr, t_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_patch_targets(ctx, e_dev_ptr, scale_dev_ptr, t_dev_ptr, stream))
+
+
+def mfe_patch_scatter(ctx, y_dev_ptr, scale_dev_ptr, alpha, z_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_patch_scatter(ctx, y_dev_ptr, scale_dev_ptr, float(alpha), z_dev_ptr, stream))
+
+
+def mfe_patch_adjoint(ctx, g_dev_ptr, scale_dev_ptr, alpha, dy_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_patch_adjoint(ctx, g_dev_ptr, scale_dev_ptr, float(alpha), dy_dev_ptr, stream))
+
+
+def _check_free(rc, what):
+    if rc != MFE_OK:
+        raise MfeError(rc, what)
+    return rc
+
+
+def mfe_net_forward(params_ptr, x_ptr, n_patches, act_ptr, y_ptr, variant=MFE_NET_RELU, stream=None):
+    return _check_free(_lib.mfe_net_forward(params_ptr, x_ptr, int(n_patches), int(variant), act_ptr, y_ptr, stream),
+                       "mfe_net_forward")
+
+
+def mfe_net_backward(params_ptr, x_ptr, act_ptr, dy_ptr, n_patches, work_ptr, grad_ptr, variant=MFE_NET_RELU,
+                     stream=None):
+    return _check_free(_lib.mfe_net_backward(params_ptr, x_ptr, act_ptr, dy_ptr, int(n_patches), int(variant),
+                                             work_ptr, grad_ptr, stream), "mfe_net_backward")
+
+
+def mfe_net_loss(y_ptr, t_ptr, n, dy_ptr, scratch_ptr, stream=None) -> float:
+    loss = _d()
+    _check_free(_lib.mfe_net_loss(y_ptr, t_ptr, int(n), dy_ptr, scratch_ptr, ctypes.byref(loss), stream),
+                "mfe_net_loss")
+    return loss.value
+
+
+def mfe_net_adam(params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, stream=None):
+    return _check_free(_lib.mfe_net_adam(params_ptr, grad_ptr, m_ptr, v_ptr, int(step), float(lr), stream),
+                       "mfe_net_adam")
 
 
 def mfe_cg_solve(ctx, opts: SolveOpts, b_dev_ptr, x_dev_ptr, stream=None):
@@ -375,6 +441,53 @@ class Operator:
                                    _dev_f64(x, self.n_dofs, "x"), _stream_handle(stream))
         return x, it, rel, STATUS_NAMES.get(rc, rc)
 
+    # ---------------------------------------------------------- learned correction
+    def set_network(self, params, variant="relu"):
+        """Network parameters for the "gmg_net" preconditioner (MFE_NET_PARAMS floats, host or device; None
+        clears) and its variant ("relu" or "linear")."""
+        import numpy as np
+        var = NET_VARIANTS.get(variant, variant)
+        if params is None:
+            mfe_set_network(self.ctx, None, var)
+            return
+        if hasattr(params, "detach"):
+            params = params.detach().cpu().numpy()
+        h = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if h.size != MFE_NET_PARAMS:
+            raise ValueError(f"expected {MFE_NET_PARAMS} parameters")
+        mfe_set_network(self.ctx, h.ctypes.data, var)
+
+    @property
+    def n_patches(self):
+        return mfe_patch_count(self.ctx)
+
+    def patch_features(self, r, variant="relu", stream=None):
+        """(feat [P,6,729] float32, scale [P] float32) of a residual r at the current state."""
+        import torch
+        P = self.n_patches
+        feat = torch.empty((P, 6, 729), dtype=torch.float32, device=r.device)
+        scale = torch.empty(P, dtype=torch.float32, device=r.device)
+        mfe_patch_features(self.ctx, _dev_f64(r, self.n_dofs, "r"), feat.data_ptr(), scale.data_ptr(),
+                           NET_VARIANTS.get(variant, variant), _stream_handle(stream))
+        return feat, scale
+
+    def patch_targets(self, e, scale, stream=None):
+        import torch
+        t = torch.empty((self.n_patches, 3, 729), dtype=torch.float32, device=e.device)
+        mfe_patch_targets(self.ctx, _dev_f64(e, self.n_dofs, "e"), scale.data_ptr(), t.data_ptr(),
+                          _stream_handle(stream))
+        return t
+
+    def patch_scatter(self, y, scale, z, alpha=1.0, stream=None):
+        mfe_patch_scatter(self.ctx, y.data_ptr(), scale.data_ptr(), alpha, _dev_f64(z, self.n_dofs, "z"),
+                          _stream_handle(stream))
+        return z
+
+    def patch_adjoint(self, g, scale, dy, alpha=1.0, stream=None):
+        mfe_patch_adjoint(self.ctx, _dev_f64(g, self.n_dofs, "g"), scale.data_ptr(), alpha, dy.data_ptr(),
+                          _stream_handle(stream))
+        return dy
+
     def gmg_setup(self, stream=None, **opts):
         """Set up the multigrid level data at the current state (as a GMG CG solve does)."""
         mfe_gmg_setup(self.ctx, self.solve_opts(preconditioner="gmg", **opts), _stream_handle(stream))
@@ -401,7 +514,7 @@ class Operator:
                   _stream_handle(stream))
         return y
 
-    def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, **opts):
+    def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, on_step=None, **opts):
         """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping).
 
         boundary_values(t) -> (dofs, values): prescribed values at load t on the
@@ -412,6 +525,7 @@ class Operator:
         each step starts from the linear extrapolation of the two previous
         converged states.
         u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
+        on_step(t, u), if given, is called after every converged step.
         Returns a list of per-step reports (dicts with t, h and the solver report).
         """
         import numpy as np
@@ -441,6 +555,8 @@ class Operator:
                 prev_h = h
                 t += h
                 reports.append(dict(t=t, h=h, **rep))
+                if on_step is not None:
+                    on_step(t, u)
                 h = min(h_cap, 1.25 * h)
             else:
                 reports.append(dict(t=t + h, h=h, failed=True, **rep))

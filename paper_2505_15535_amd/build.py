@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfe.so")
-SOURCES = ["mfe_kernels.hip", "mfe_solver.hip", "mfe_mg.hip", "mfe_api.hip"]
+SOURCES = ["mfe_kernels.hip", "mfe_solver.hip", "mfe_mg.hip", "mfe_net.hip", "mfe_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

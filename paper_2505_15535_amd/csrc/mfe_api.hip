@@ -268,6 +268,19 @@ struct mfe_ctx {
     // what the level data were last set up for
     uint64_t mg_ready_version = 0;
     int mg_ready_strategy = -1, mg_ready_prec = -1;
+    // learned smoother correction: network parameters, node invariants of the
+    // state, per-patch buffers of the preconditioner
+    float* d_net = nullptr;
+    int net_variant = MFE_NET_RELU;
+    double net_alpha = 0.0;      // linear variant: step length frozen for one CG solve
+    bool net_alpha_set = false;
+    bool net_off = false;        // set when a solve had to drop the correction; cleared by mfe_set_network
+    float* d_ninv = nullptr;     // [n_nodes][3] I1, I2, J
+    float* d_cinv = nullptr;     // [ne][3] scratch
+    uint64_t ninv_version = 0;
+    bool ninv_valid = false;
+    float* d_nbuf = nullptr;     // features, two hidden layers, output, scale
+    double* d_fcg = nullptr;     // flexible CG directions and their images
     // timing of the apply kernel
     bool timing = false;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -327,6 +340,11 @@ void free_mesh_data(mfe_ctx* c) {
     mg_free(c);
     dfree(c->d_work);
     dfree(c->d_energy);
+    dfree(c->d_ninv);
+    dfree(c->d_cinv);
+    dfree(c->d_nbuf);
+    dfree(c->d_fcg);
+    c->ninv_valid = false;
     dfree(c->d_verts);
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
@@ -399,6 +417,7 @@ void mfe_destroy(mfe_ctx* c) {
     free_mesh_data(c);
     dfree(c->d_flag);
     dfree(c->d_work);
+    dfree(c->d_net);
     dfree(c->d_partials);
     dfree(c->d_bad);
     if (c->h_scalars) (void)hipHostFree(c->h_scalars);
@@ -722,7 +741,7 @@ int mfe_energy(mfe_ctx* c, const double* u, double* energy, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nb = (int64_t)c->nbx * c->nby * c->nbz;
     if (!c->d_energy) MFE_HIP(c, hipMalloc(&c->d_energy, (nb + 1) * sizeof(double)));
-    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 4 * sizeof(double), hipHostMallocDefault));
+    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 16 * sizeof(double), hipHostMallocDefault));
     KParams p = base_params(c);
     p.u = u;
     p.v = c->d_energy;
@@ -757,10 +776,12 @@ int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
 namespace {
 
 int ensure_work(mfe_ctx* c) {
-    if (!c->d_work) MFE_HIP(c, hipMalloc(&c->d_work, 8 * c->n_dofs * sizeof(double)));
-    if (!c->d_partials) MFE_HIP(c, hipMalloc(&c->d_partials, (2 * mfe::kDotBlocks + 2) * sizeof(double)));
+    // 11 vectors: CG r, z, p, Kp, 1/diag; Newton R, du, dg; learned
+    // preconditioner N, K z (then K N), r - K z
+    if (!c->d_work) MFE_HIP(c, hipMalloc(&c->d_work, 11 * c->n_dofs * sizeof(double)));
+    if (!c->d_partials) MFE_HIP(c, hipMalloc(&c->d_partials, (2 * mfe::kDotBlocks + 16) * sizeof(double)));
     if (!c->d_bad) MFE_HIP(c, hipMalloc(&c->d_bad, sizeof(int)));
-    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 4 * sizeof(double), hipHostMallocDefault));
+    if (!c->h_scalars) MFE_HIP(c, hipHostMalloc(&c->h_scalars, 16 * sizeof(double), hipHostMallocDefault));
     return MFE_OK;
 }
 
@@ -784,9 +805,9 @@ int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const do
 int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
     if (!o) return fail(c, MFE_EINVAL, "null options");
     if (o->strategy < MFE_OTF || o->strategy > MFE_OTF_AD) return fail(c, MFE_EINVAL, "unknown strategy");
-    if (o->preconditioner < MFE_PC_NONE || o->preconditioner > MFE_PC_GMG)
+    if (o->preconditioner < MFE_PC_NONE || o->preconditioner > MFE_PC_GMG_NET)
         return fail(c, MFE_EINVAL, "unknown preconditioner");
-    if (o->preconditioner == MFE_PC_GMG) {
+    if (o->preconditioner == MFE_PC_GMG || o->preconditioner == MFE_PC_GMG_NET) {
         if (o->mg_levels < 0) return fail(c, MFE_EINVAL, "mg_levels must be >= 0");
         if (o->cheb_degree < 1 || o->coarse_degree < 1) return fail(c, MFE_EINVAL, "Chebyshev degrees must be >= 1");
         if (!(o->cheb_range > 1.0) || !(o->coarse_range > 1.0) || !std::isfinite(o->cheb_range) ||
@@ -1340,20 +1361,212 @@ int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, h
     return MFE_OK;
 }
 
-// z = B r with the GMG hierarchy of c, then r.z (must be positive)
-int gmg_precondition(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s, double& rz) {
+
+// ------------------------------------------------------- learned correction
+// Network layout: conv 6->32 (ReLU), conv 32->32 (ReLU), conv 32->3, 3x3x3
+// kernels on the 9^3 nodes of a patch of 4^3 Q2 cells; W[co][ci][27] then
+// bias[co] per layer.
+constexpr int kNetW1 = 0, kNetB1 = 5184, kNetW2 = 5216, kNetB2 = 32864, kNetW3 = 32896, kNetB3 = 35488;
+constexpr int kNetParams = 35491;
+constexpr int64_t kPatchVox = 729;
+
+int patch_dims(const mfe_ctx* c, int& npx, int& npy, int& npz) {
+    npx = npy = npz = 0;
+    if (!c->has_mesh || c->degree != 2 || c->nx % 4 || c->ny % 4 || c->nz % 4) return 0;
+    npx = c->nx / 4;
+    npy = c->ny / 4;
+    npz = c->nz / 4;
+    return npx * npy * npz;
+}
+
+// variant MFE_NET_RELU: ReLU after layers 1 and 2, biases; MFE_NET_LINEAR:
+// neither (the biases are not read), so y is a linear function of x
+hipError_t net_forward(const float* prm, const float* x, int P, int variant, float* act, float* y, hipStream_t s) {
+    const bool nl = variant == MFE_NET_RELU;
+    float* a1 = act;
+    float* a2 = act + (int64_t)P * 32 * kPatchVox;
+    hipError_t e = mfe::launch_conv3d(x, prm + kNetW1, nl ? prm + kNetB1 : nullptr, P, 6, 32, false, nl, nullptr, a1, s);
+    if (e == hipSuccess)
+        e = mfe::launch_conv3d(a1, prm + kNetW2, nl ? prm + kNetB2 : nullptr, P, 32, 32, false, nl, nullptr, a2, s);
+    if (e == hipSuccess)
+        e = mfe::launch_conv3d(a2, prm + kNetW3, nl ? prm + kNetB3 : nullptr, P, 32, 3, false, false, nullptr, y, s);
+    return e;
+}
+
+hipError_t net_backward(const float* prm, const float* x, const float* act, const float* dy, int P, int variant,
+                        float* work, float* grad, hipStream_t s) {
+    const bool nl = variant == MFE_NET_RELU;
+    const float* a1 = act;
+    const float* a2 = act + (int64_t)P * 32 * kPatchVox;
+    float* d1 = work;
+    float* d2 = work + (int64_t)P * 32 * kPatchVox;
+    hipError_t e = mfe::launch_conv3d_wgrad(a2, dy, P, 32, 3, grad + kNetW3, grad + kNetB3, s);
+    if (e == hipSuccess) e = mfe::launch_conv3d(dy, prm + kNetW3, nullptr, P, 3, 32, true, false, nl ? a2 : nullptr, d2, s);
+    if (e == hipSuccess) e = mfe::launch_conv3d_wgrad(a1, d2, P, 32, 32, grad + kNetW2, grad + kNetB2, s);
+    if (e == hipSuccess) e = mfe::launch_conv3d(d2, prm + kNetW2, nullptr, P, 32, 32, true, false, nl ? a1 : nullptr, d1, s);
+    if (e == hipSuccess) e = mfe::launch_conv3d_wgrad(x, d1, P, 6, 32, grad + kNetW1, grad + kNetB1, s);
+    if (e == hipSuccess && !nl) {  // biases are not part of the linear variant
+        e = mfe::launch_fill(grad + kNetB1, 32, 0.0f, s);
+        if (e == hipSuccess) e = mfe::launch_fill(grad + kNetB2, 32, 0.0f, s);
+        if (e == hipSuccess) e = mfe::launch_fill(grad + kNetB3, 3, 0.0f, s);
+    }
+    return e;
+}
+
+// node invariants (I1, I2, J of C = F^T F) of the current state
+int ensure_node_invariants(mfe_ctx* c, hipStream_t s) {
+    if (c->ninv_valid && c->ninv_version == c->state_version) return MFE_OK;
+    if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
+    if (!c->d_ninv) MFE_HIP(c, hipMalloc(&c->d_ninv, 3 * c->n_nodes * sizeof(float)));
+    if (!c->d_cinv) MFE_HIP(c, hipMalloc(&c->d_cinv, 3 * c->ne * sizeof(float)));
+    MFE_HIP(c, mfe::launch_node_invariants(c->d_u, c->d_verts, c->nx, c->ny, c->nz, c->Nx, c->Ny, c->Nz, c->d_cinv,
+                                           c->d_ninv, s));
+    c->ninv_valid = true;
+    c->ninv_version = c->state_version;
+    return MFE_OK;
+}
+
+// z += alpha N, the learned correction N of the residual r1 = r - K z left by
+// the V-cycle (z holds V r): features of every patch, the network, the
+// patch-averaged scatter, N = 0 at constrained dofs; alpha = N.r1 / N.K N
+// minimises the energy norm of the error along N, so the step never makes
+// the error larger (it is skipped when N.r1 <= 0 or N.K N <= 0).
+int net_correct(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s) {
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    const int64_t n = c->n_dofs;
+    double* Kv = c->d_work + 9 * n;   // K z, then K N
+    double* r1 = c->d_work + 10 * n;  // r - K z
+    double* N = c->d_work + 8 * n;    // the correction
+    int rc = ensure_node_invariants(c, s);
+    if (rc != MFE_OK) return rc;
+    const int64_t per = (int64_t)P * kPatchVox;
+    if (!c->d_nbuf) MFE_HIP(c, hipMalloc(&c->d_nbuf, ((6 + 64 + 3) * per + P) * sizeof(float)));
+    float* feat = c->d_nbuf;
+    float* act = feat + 6 * per;
+    float* y = act + 64 * per;
+    float* scale = y + 3 * per;
+    rc = mfe_apply_tangent(c, z, Kv, o->strategy, MFE_FP64, s);
+    if (rc != MFE_OK) return rc;
+    MFE_HIP(c, mfe::launch_copy(r, r1, n, s));
+    MFE_HIP(c, mfe::launch_axpby(-1.0, Kv, 1.0, r1, n, s));
+    const bool linear = c->net_variant == MFE_NET_LINEAR;
+    MFE_HIP(c, mfe::launch_patch_features(r1, c->d_ninv, c->Nx, c->Ny, npx, npy, P, linear, feat, scale, s));
+    MFE_HIP(c, net_forward(c->d_net, feat, P, c->net_variant, act, y, s));
+    MFE_HIP(c, mfe::launch_fill(N, n, 0.0, s));
+    MFE_HIP(c, mfe::launch_patch_scatter(y, scale, c->Nx, c->Ny, c->Nz, npx, npy, npz, 1.0, N, s));
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, N, s));
+    if (linear && c->net_alpha_set) {  // a fixed linear preconditioner within the solve
+        if (c->net_alpha > 0.0) MFE_HIP(c, mfe::launch_axpby(c->net_alpha, N, 1.0, z, n, s));
+        return MFE_OK;
+    }
+    rc = mfe_apply_tangent(c, N, Kv, o->strategy, MFE_FP64, s);
+    if (rc != MFE_OK) return rc;
+    double nr, nkn;
+    rc = dot2(c, N, r1, N, Kv, s, nr, nkn);
+    if (rc != MFE_OK) return rc;
+    const bool ok = nr > 0.0 && nkn > 0.0 && std::isfinite(nr) && std::isfinite(nkn);
+    if (ok) MFE_HIP(c, mfe::launch_axpby(nr / nkn, N, 1.0, z, n, s));
+    if (linear) {
+        c->net_alpha = ok ? nr / nkn : 0.0;
+        c->net_alpha_set = true;
+    }
+    return MFE_OK;
+}
+
+// z = B r (GMG V-cycle, plus the learned correction when `net`), then r.z > 0
+int precondition(mfe_ctx* c, const mfe_solve_opts* o, bool net, const double* r, double* z, hipStream_t s,
+                 double& rz) {
     int rc = gmg_apply(c, o, r, z, s);
     if (rc != MFE_OK) return rc;
+    if (net) {
+        rc = net_correct(c, o, r, z, s);
+        if (rc != MFE_OK) return rc;
+    }
     double unused;
     rc = dot2(c, r, z, nullptr, nullptr, s, rz, unused);
     if (rc != MFE_OK) return rc;
-    if (!(rz > 0.0)) return fail(c, MFE_ENOTCONV, "multigrid preconditioner is not positive definite");
+    if (!(rz > 0.0)) return fail(c, MFE_ENOTCONV, "preconditioner is not positive definite");
     return MFE_OK;
+}
+
+// Flexible CG (truncated, the last kMaxDirs directions kept K-orthogonal)
+// for the preconditioner with the learned correction, which is not a fixed
+// linear operator: z = B r, p = z - sum_j (z.K p_j / p_j.K p_j) p_j,
+// alpha = p.r / p.K p.  x starts at 0, r = b, z = B b on entry.  The learned
+// part is dropped (net = false) when the residual stagnates.
+int fcg(mfe_ctx* c, const mfe_solve_opts* o, bool net, double* x, double* r, double* z, double bnorm,
+        hipStream_t s, int& iters, double& rel, int* net_fallbacks) {
+    const int64_t n = c->n_dofs;
+    constexpr int M = mfe::kMaxDirs;
+    if (!c->d_fcg) MFE_HIP(c, hipMalloc(&c->d_fcg, 2 * (int64_t)M * n * sizeof(double)));
+    double* Pd = c->d_fcg;             // directions, M rows
+    double* KPd = c->d_fcg + M * n;    // their images under K
+    double pkp[M];
+    double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    std::vector<double> rel_hist;
+    int have = 0, head = 0;  // ring buffer of directions
+    int rc;
+    for (int it = 1; it <= o->max_cg; ++it) {
+        // p = z orthogonalised against the stored directions (in ring order)
+        const int slot = head;
+        double* p = Pd + (int64_t)slot * n;
+        double* Kp = KPd + (int64_t)slot * n;
+        mfe::DirCoeffs cf{};
+        if (have > 0) {
+            // only the `have` rows written so far are read (rows 0..have-1)
+            MFE_HIP(c, mfe::launch_multidot(z, KPd, have, n, c->d_partials, out, s));
+            MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, have * sizeof(double), hipMemcpyDeviceToHost, s));
+            MFE_HIP(c, hipStreamSynchronize(s));
+            for (int j = 0; j < M; ++j) {
+                const bool used = j < have && j != slot;
+                cf.c[j] = used ? c->h_scalars[j] / pkp[j] : 0.0;
+            }
+        }
+        MFE_HIP(c, mfe::launch_multi_axpy(z, Pd, cf, have, n, p, s));
+        rc = mfe_apply_tangent(c, p, Kp, o->strategy, MFE_FP64, s);
+        if (rc != MFE_OK) return rc;
+        double pr, pKp;
+        rc = dot2(c, p, r, p, Kp, s, pr, pKp);
+        if (rc != MFE_OK) return rc;
+        if (!(pKp > 0.0)) return fail(c, MFE_ENOTCONV, "CG breakdown: p.Kp <= 0 (tangent not positive definite)");
+        pkp[slot] = pKp;
+        head = (head + 1) % M;
+        have = std::min(have + 1, M);
+        const double alpha = pr / pKp;
+        double* out2 = c->d_partials + 2 * mfe::kDotBlocks;
+        MFE_HIP(c, mfe::launch_cg_update(x, r, z, p, Kp, nullptr, alpha, n, c->d_partials, out2, s));
+        MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out2, sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipStreamSynchronize(s));
+        iters = it;
+        rel = std::sqrt(c->h_scalars[0]) / bnorm;
+        if (rel <= o->cg_rtol) return MFE_OK;
+        if (net) {  // stagnation: less than 10% residual reduction over the last 3 iterations
+            rel_hist.push_back(rel);
+            const size_t k = rel_hist.size();
+            if (k >= 4 && rel_hist[k - 1] > 0.9 * rel_hist[k - 4]) {
+                net = false;
+                c->net_off = true;
+                if (net_fallbacks) ++*net_fallbacks;
+            }
+        }
+        double rz;
+        rc = precondition(c, o, net, r, z, s, rz);
+        if (rc == MFE_ENOTCONV && net) {
+            net = false;
+            c->net_off = true;
+            if (net_fallbacks) ++*net_fallbacks;
+            c->err.clear();
+            rc = precondition(c, o, false, r, z, s, rz);
+        }
+        if (rc != MFE_OK) return rc;
+    }
+    return fail(c, MFE_ENOTCONV, "CG did not reach its tolerance");
 }
 
 // preconditioned CG on K(u) x = b, x starts at 0.  Work vectors: r, z, p, Ap, dinv.
 int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStream_t s, int& iters, double& rel,
-       int* fallbacks = nullptr) {
+       int* fallbacks = nullptr, int* net_fallbacks = nullptr) {
     const int64_t n = c->n_dofs;
     double* r = c->d_work + 0 * n;
     double* z = c->d_work + 1 * n;
@@ -1363,8 +1576,21 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     iters = 0;
     rel = 0.0;
     bool jac = o->preconditioner == MFE_PC_JACOBI;
-    bool gmg = o->preconditioner == MFE_PC_GMG;
+    bool gmg = o->preconditioner == MFE_PC_GMG || o->preconditioner == MFE_PC_GMG_NET;
+    // learned correction on top of the V-cycle: flexible CG (the preconditioner
+    // is not linear), dropped for the rest of the solve when it stops helping
+    // once a solve on this context had to drop the correction, later solves
+    // use the plain V-cycle until a network is set again
+    bool net = o->preconditioner == MFE_PC_GMG_NET && !c->net_off;
+    const bool flexible = net;
     int rc;
+    if (net) {
+        int npx, npy, npz;
+        c->net_alpha_set = false;  // a new solve: the linear variant's step is chosen again
+        if (!c->d_net) return fail(c, MFE_EINVAL, "no network set (mfe_set_network)");
+        if (patch_dims(c, npx, npy, npz) == 0)
+            return fail(c, MFE_EUNSUPPORTED, "the learned correction needs Q2 and cell counts divisible by 4");
+    }
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, b, r, n, s));
     if (gmg) {
@@ -1377,10 +1603,17 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         rc = mg_update(c, o, s);
         if (rc == MFE_OK) {
             double unused;
-            rc = gmg_precondition(c, o, r, z, s, unused);
+            rc = precondition(c, o, net, r, z, s, unused);
+            if (rc == MFE_ENOTCONV && net) {  // try without the learned part
+                net = false;
+                c->net_off = true;
+                if (net_fallbacks) ++*net_fallbacks;
+                c->err.clear();
+                rc = precondition(c, o, false, r, z, s, unused);
+            }
         }
         if (rc == MFE_ENOTCONV || rc == MFE_EJACOBIAN) {
-            gmg = false;
+            gmg = net = false;
             jac = true;
             if (fallbacks) ++*fallbacks;
             c->err.clear();
@@ -1407,6 +1640,7 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     if (rc != MFE_OK) return rc;
     const double bnorm = std::sqrt(rr);
     if (bnorm == 0.0) return MFE_OK;
+    if (flexible && gmg) return fcg(c, o, net, x, r, z, bnorm, s, iters, rel, net_fallbacks);
     double* out = c->d_partials + 2 * mfe::kDotBlocks;
     for (int it = 1; it <= o->max_cg; ++it) {
         rc = mfe_apply_tangent(c, pv, Ap, o->strategy, MFE_FP64, s);
@@ -1430,7 +1664,7 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         rel = std::sqrt(rr) / bnorm;
         if (rel <= o->cg_rtol) return MFE_OK;
         if (gmg) {
-            rc = gmg_precondition(c, o, r, z, s, rz_new);
+            rc = precondition(c, o, false, r, z, s, rz_new);
             if (rc != MFE_OK) return rc;
         }
         MFE_HIP(c, mfe::launch_axpby(1.0, z, rz_new / rz, pv, n, s));
@@ -1610,7 +1844,7 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
         }
         int iters = 0;
         double rel = 0.0;
-        rc = cg(c, o, res, du, s, iters, rel, &local.pc_fallbacks);
+        rc = cg(c, o, res, du, s, iters, rel, &local.pc_fallbacks, &local.net_fallbacks);
         local.cg_iterations += iters;
         if (rc != MFE_OK && rc != MFE_ENOTCONV) { status = rc; break; }
         c->err.clear();
@@ -1704,6 +1938,129 @@ double mfe_apply_kernel_ms(mfe_ctx* c, int* count_out) {
     }
     if (count_out) *count_out = c->ev_used;
     return total / c->ev_used;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned correction
+extern "C" {
+
+int mfe_set_network(mfe_ctx* c, const float* params_host, int variant) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (variant != MFE_NET_RELU && variant != MFE_NET_LINEAR) return fail(c, MFE_EINVAL, "unknown network variant");
+    c->net_variant = variant;
+    c->net_off = false;
+    DeviceGuard g(c->device);
+    if (!params_host) {
+        dfree(c->d_net);
+        return MFE_OK;
+    }
+    for (int i = 0; i < kNetParams; ++i)
+        if (!std::isfinite(params_host[i])) return fail(c, MFE_EINVAL, "non-finite network parameter");
+    if (!c->d_net) MFE_HIP(c, hipMalloc(&c->d_net, kNetParams * sizeof(float)));
+    MFE_HIP(c, hipMemcpy(c->d_net, params_host, kNetParams * sizeof(float), hipMemcpyHostToDevice));
+    return MFE_OK;
+}
+
+int64_t mfe_patch_count(const mfe_ctx* c) {
+    if (!c) return 0;
+    int npx, npy, npz;
+    return patch_dims(c, npx, npy, npz);
+}
+
+int mfe_patch_features(mfe_ctx* c, const double* r, float* feat, float* scale, int variant, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    if (P == 0) return fail(c, MFE_EUNSUPPORTED, "patches need Q2 and cell counts divisible by 4");
+    if (!r || !feat || !scale) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = ensure_node_invariants(c, s);
+    if (rc != MFE_OK) return rc;
+    MFE_HIP(c, mfe::launch_patch_features(r, c->d_ninv, c->Nx, c->Ny, npx, npy, P, variant == MFE_NET_LINEAR, feat,
+                                          scale, s));
+    return MFE_OK;
+}
+
+int mfe_patch_targets(mfe_ctx* c, const double* e, const float* scale, float* t, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    if (P == 0) return fail(c, MFE_EUNSUPPORTED, "patches need Q2 and cell counts divisible by 4");
+    if (!e || !scale || !t) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard g(c->device);
+    MFE_HIP(c, mfe::launch_patch_targets(e, scale, c->Nx, c->Ny, npx, npy, P, t, static_cast<hipStream_t>(stream)));
+    return MFE_OK;
+}
+
+int mfe_patch_scatter(mfe_ctx* c, const float* y, const float* scale, double alpha, double* z, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    if (P == 0) return fail(c, MFE_EUNSUPPORTED, "patches need Q2 and cell counts divisible by 4");
+    if (!y || !scale || !z) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard g(c->device);
+    MFE_HIP(c, mfe::launch_patch_scatter(y, scale, c->Nx, c->Ny, c->Nz, npx, npy, npz, alpha, z,
+                                         static_cast<hipStream_t>(stream)));
+    return MFE_OK;
+}
+
+int mfe_patch_adjoint(mfe_ctx* c, const double* g, const float* scale, double alpha, float* dy, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    if (P == 0) return fail(c, MFE_EUNSUPPORTED, "patches need Q2 and cell counts divisible by 4");
+    if (!g || !scale || !dy) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard gd(c->device);
+    MFE_HIP(c, mfe::launch_patch_adjoint(g, scale, c->Nx, c->Ny, npx, npy, npz, P, (float)alpha, dy,
+                                         static_cast<hipStream_t>(stream)));
+    return MFE_OK;
+}
+
+int mfe_net_forward(const float* params, const float* x, int n_patches, int variant, float* act, float* y,
+                    void* stream) {
+    if (!params || !x || !act || !y || n_patches < 0) return MFE_EINVAL;
+    if (variant != MFE_NET_RELU && variant != MFE_NET_LINEAR) return MFE_EINVAL;
+    return net_forward(params, x, n_patches, variant, act, y, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? MFE_OK
+               : MFE_EHIP;
+}
+
+int mfe_net_backward(const float* params, const float* x, const float* act, const float* dy, int n_patches,
+                     int variant, float* work, float* grad, void* stream) {
+    if (!params || !x || !act || !dy || !work || !grad || n_patches < 1) return MFE_EINVAL;
+    if (variant != MFE_NET_RELU && variant != MFE_NET_LINEAR) return MFE_EINVAL;
+    return net_backward(params, x, act, dy, n_patches, variant, work, grad, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? MFE_OK
+               : MFE_EHIP;
+}
+
+int mfe_net_loss(const float* y, const float* t, int64_t n, float* dy, double* scratch, double* loss, void* stream) {
+    if (!y || !t || !scratch || !loss || n < 1) return MFE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = mfe::mse_blocks(n);
+    if (mfe::launch_mse(y, t, n, dy, scratch, s) != hipSuccess) return MFE_EHIP;
+    if (mfe::launch_sum(scratch, nb, scratch + 1024, s) != hipSuccess) return MFE_EHIP;
+    double h = 0.0;
+    if (hipMemcpyAsync(&h, scratch + 1024, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return MFE_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MFE_EHIP;
+    *loss = h / (double)n;
+    return MFE_OK;
+}
+
+int mfe_net_adam(float* params, const float* grad, float* m, float* v, int step, float lr, void* stream) {
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return MFE_EINVAL;
+    return mfe::launch_adam(params, grad, m, v, kNetParams, lr, 0.9f, 0.999f, 1e-8f, step,
+                            static_cast<hipStream_t>(stream)) == hipSuccess
+               ? MFE_OK
+               : MFE_EHIP;
 }
 
 }  // extern "C"

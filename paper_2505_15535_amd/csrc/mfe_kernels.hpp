@@ -93,6 +93,17 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
 // d = 1/d (1/|d| with absolute); *bad = 1 where that is not positive and finite
+// Flexible CG with a window of kMaxDirs earlier directions: out[j] = z . Y[j]
+// (Y: m rows of n, m <= kMaxDirs; partials need m * 256 doubles), and
+// p = z - sum_j c[j] P[j].
+constexpr int kMaxDirs = 8;
+struct DirCoeffs {
+    double c[kMaxDirs];
+};
+hipError_t launch_multidot(const double* z, const double* Y, int m, int64_t n, double* partials, double* out,
+                           hipStream_t s);
+hipError_t launch_multi_axpy(const double* z, const double* P, const DirCoeffs& c, int m, int64_t n, double* p,
+                             hipStream_t s);
 // out[0] = sum of x[0..n) (one workgroup, fixed order)
 hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s);
 hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s, bool absolute = false);
@@ -120,6 +131,27 @@ hipError_t launch_copy(const float* x, float* y, int64_t n, hipStream_t s);
 hipError_t launch_axpby(float a, const float* x, float b, float* y, int64_t n, hipStream_t s);
 hipError_t launch_convert(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_convert(const float* src, double* dst, int64_t n, hipStream_t s);
+// Learned smoother correction (mfe_net.hip): patches of 4x4x4 Q2 cells
+// (9^3 nodes), activations [patch][channel][729].
+hipError_t launch_conv3d(const float* x, const float* W, const float* bias, int P, int CI, int CO, bool flip,
+                         bool relu, const float* mask, float* y, hipStream_t s);
+hipError_t launch_conv3d_wgrad(const float* x, const float* dy, int P, int CI, int CO, float* dW, float* db,
+                               hipStream_t s);
+int mse_blocks(int64_t n);
+hipError_t launch_mse(const float* y, const float* t, int64_t n, float* dy, double* partial, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_patch_features(const double* r, const float* inv, int Nx, int Ny, int npx, int npy, int P,
+                                 bool linear, float* feat, float* scale, hipStream_t s);
+hipError_t launch_patch_targets(const double* e, const float* scale, int Nx, int Ny, int npx, int npy, int P,
+                                float* t, hipStream_t s);
+hipError_t launch_patch_scatter(const float* y, const float* scale, int Nx, int Ny, int Nz, int npx, int npy,
+                                int npz, double alpha, double* z, hipStream_t s);
+hipError_t launch_patch_adjoint(const double* g, const float* scale, int Nx, int Ny, int npx, int npy, int npz,
+                                int P, float alpha, float* dy, hipStream_t s);
+hipError_t launch_node_invariants(const double* u, const double* verts, int nx, int ny, int nz, int Nx, int Ny,
+                                  int Nz, float* cell_scratch, float* ninv, hipStream_t s);
+
 hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const double* src, double* dst,
                                hipStream_t stream);
 hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const float* src, float* dst, hipStream_t stream);

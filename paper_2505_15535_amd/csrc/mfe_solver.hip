@@ -122,6 +122,44 @@ __global__ void invert_kernel(double* __restrict__ d, int64_t n, int* __restrict
     }
 }
 
+// partials[j * nb + b] = sum over block b of z . Y[j] (Y: m rows of n), j < m <= kMaxDirs
+__global__ __launch_bounds__(kRedThreads) void multidot_kernel(const double* __restrict__ z,
+                                                               const double* __restrict__ Y, int m, int64_t n,
+                                                               double* __restrict__ partials) {
+    __shared__ double sh[kRedThreads / 64];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int j = 0; j < m; ++j) {
+        const double* y = Y + (int64_t)j * n;
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc = fma(z[i], y[i], acc);
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) partials[(int64_t)j * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// out[j] = sum of partials[j * nb .. j * nb + nb) (fixed order)
+__global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double* __restrict__ partials, int nb, int m,
+                                                                  double* __restrict__ out) {
+    __shared__ double sh[kRedThreads / 64];
+    for (int j = 0; j < m; ++j) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[(int64_t)j * nb + i];
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) out[j] = t;
+    }
+}
+
+// p = z - sum_j c[j] P[j]
+__global__ void multi_axpy_kernel(const double* __restrict__ z, const double* __restrict__ P, DirCoeffs c, int m,
+                                  int64_t n, double* __restrict__ p) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double v = z[i];
+        for (int j = 0; j < m; ++j) v = fma(-c.c[j], P[(int64_t)j * n + i], v);
+        p[i] = v;
+    }
+}
+
 static unsigned grid_for(int64_t n) {
     int64_t b = (n + kRedThreads - 1) / kRedThreads;
     return (unsigned)(b > kDotBlocks ? kDotBlocks : (b < 1 ? 1 : b));
@@ -141,6 +179,20 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
     hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, s, x, r, z, p, Ap, dinv, alpha, n,
                        partials);
     hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(const double* z, const double* Y, int m, int64_t n, double* partials, double* out,
+                           hipStream_t s) {
+    const unsigned nb = grid_for(n) > 256 ? 256 : grid_for(n);  // m * nb partials fit the 2 kDotBlocks scratch
+    hipLaunchKernelGGL(multidot_kernel, dim3(nb), dim3(kRedThreads), 0, s, z, Y, m, n, partials);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(const double* z, const double* P, const DirCoeffs& c, int m, int64_t n, double* p,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, z, P, c, m, n, p);
     return hipGetLastError();
 }
 

@@ -1,0 +1,222 @@
+"""Training data, training loop and evaluation of the learned smoother
+correction (preconditioner "gmg_net").
+
+The correction acts after a GMG V-cycle: with z = V r, the residual left is
+r1 = r - K z, and the network maps the patch features of r1 (residual scaled
+by its patch RMS, strain invariants of the state) to a correction N(r1),
+assembled from the patch outputs by averaging over shared nodes.  Its quality
+is the energy norm of the error it leaves, ||e1 - N||_K^2 with e1 = K^-1 r1,
+which equals 2 J(N) + e1.r1 with J(N) = N.K N / 2 - N.r1: the loss is J, the
+potential energy of the correction, whose gradient K N - r1 is the residual
+after the correction -- no solved target is needed, and the norm weights the
+local (high-frequency) part of the error that a patch network can represent,
+not the smooth part that the coarse grid already handles.  Residuals r1 come
+from the Newton-CG solver itself: states along twisted-beam load paths, CG
+residuals of random loads after 0-8 GMG-CG iterations, one V-cycle applied.
+Every arithmetic step runs in the library's kernels (V-cycle, applies,
+features, scatter and its adjoint, the network's forward and backward passes,
+Adam); torch only holds the buffers.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import (MFE_NET_PARAMS, NET_VARIANTS, Operator, mfe_net_adam, mfe_net_backward, mfe_net_forward,
+               mfe_net_loss)
+
+LAYERS = ((6, 32), (32, 32), (32, 3))
+
+
+def init_params(seed: int = 0, last_scale: float = 0.1) -> np.ndarray:
+    """He-normal weights (fan-in 27 ci), zero biases; the last layer scaled down."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for li, (ci, co) in enumerate(LAYERS):
+        std = np.sqrt(2.0 / (27 * ci))
+        if li == len(LAYERS) - 1:
+            std *= last_scale
+        out.append(rng.normal(0.0, std, co * ci * 27))
+        out.append(np.zeros(co))
+    p = np.concatenate(out).astype(np.float32)
+    assert p.size == MFE_NET_PARAMS
+    return p
+
+
+class Net:
+    """Parameters, Adam moments and scratch of one network on the GPU."""
+
+    def __init__(self, params: np.ndarray, device, variant="relu"):
+        import torch
+        self.device = device
+        self.variant = variant
+        self.var = NET_VARIANTS[variant]
+        self.w = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).to(device)
+        self.g = torch.zeros_like(self.w)
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.step = 0
+        self.scratch = torch.zeros(1025, dtype=torch.float64, device=device)
+        self._bufs = {}
+
+    def _buf(self, P):
+        import torch
+        if P not in self._bufs:
+            f = dict(dtype=torch.float32, device=self.device)
+            self._bufs[P] = (torch.empty((2, P, 32, 729), **f), torch.empty((P, 3, 729), **f),
+                             torch.empty((P, 3, 729), **f), torch.empty((2, P, 32, 729), **f))
+        return self._bufs[P]
+
+    def forward(self, x):
+        P = x.shape[0]
+        act, y, _, _ = self._buf(P)
+        mfe_net_forward(self.w.data_ptr(), x.data_ptr(), P, act.data_ptr(), y.data_ptr(), self.var)
+        return y
+
+    def loss(self, x, t) -> float:
+        y = self.forward(x)
+        return mfe_net_loss(y.data_ptr(), t.data_ptr(), y.numel(), None, self.scratch.data_ptr())
+
+    def train_step(self, x, t, lr) -> float:
+        P = x.shape[0]
+        act, y, dy, work = self._buf(P)
+        mfe_net_forward(self.w.data_ptr(), x.data_ptr(), P, act.data_ptr(), y.data_ptr(), self.var)
+        loss = mfe_net_loss(y.data_ptr(), t.data_ptr(), y.numel(), dy.data_ptr(), self.scratch.data_ptr())
+        mfe_net_backward(self.w.data_ptr(), x.data_ptr(), act.data_ptr(), dy.data_ptr(), P, work.data_ptr(),
+                         self.g.data_ptr(), self.var)
+        self.step += 1
+        mfe_net_adam(self.w.data_ptr(), self.g.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.step, lr)
+        return loss
+
+    def params(self) -> np.ndarray:
+        return self.w.cpu().numpy().copy()
+
+
+def beam(nx, ny, nz, lam, device=0):
+    """Operator of the twisted beam (clamped at x = 0) and its boundary data function."""
+    import synthetic
+    L = (nx / ny, 1.0, 1.0)
+    op = Operator(nx, ny, nz, 2, synthetic.box_vertices(nx, ny, nz, L), 1.0, lam, device=device)
+    cd, _ = synthetic.clamp_and_twist(nx, ny, nz, 2, L, 0.0)
+    op.set_constraints(cd)
+
+    def bv(theta_deg):
+        return lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, np.deg2rad(theta_deg) * t)
+
+    return op, bv, cd
+
+
+def residuals_at_state(op, cdofs, rng, n_loads=2, cg_stages=(0, 1, 2, 4, 8), opts=None):
+    """Unit-norm residuals r1 = r - K V r left by one V-cycle, for r = CG
+    residuals of random loads after 0, 1, 2, 4, 8 GMG-CG iterations, at the
+    operator's current state (T2 cache and level data are built here)."""
+    import torch
+    o = dict(strategy="t2", mg_precision="fp64")
+    o.update(opts or {})
+    dev = op.device
+    op.build_cache("t2")
+    op.gmg_setup(**o)
+    cd = torch.from_numpy(np.asarray(cdofs)).to(dev)
+    out = []
+    for _ in range(n_loads):
+        b0 = torch.from_numpy(rng.standard_normal(op.n_dofs)).to(dev)
+        b0[cd] = 0.0
+        for j in cg_stages:
+            if j == 0:
+                r = b0.clone()
+            else:
+                x, _, _, _ = op.cg_solve(b0, preconditioner="gmg", max_cg=j, cg_rtol=1e-30, **o)
+                r = b0 - op.apply(x, strategy="t2")
+            z = op.gmg_apply(r, **o)
+            r1 = r - op.apply(z, strategy="t2")
+            r1[cd] = 0.0
+            out.append(r1 / torch.linalg.norm(r1))
+    return out
+
+
+class Sample:
+    """One state of a load path and the residuals collected there."""
+
+    def __init__(self, u, residuals):
+        self.u = u
+        self.residuals = residuals
+
+
+def generate(paths, nx=64, ny=16, nz=16, steps=10, states_per_path=8, n_loads=2, seed=0, device=0, log=None):
+    """Samples along load paths [(theta_deg, lam), ...] of the twisted beam;
+    returns [(lam, [Sample, ...]), ...]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    out = []
+    for theta, lam in paths:
+        op, bv, cd = beam(nx, ny, nz, lam, device)
+        u = torch.zeros(op.n_dofs, dtype=torch.float64, device=op.device)
+        states = []
+        op.solve_load_path(u, bv(theta), steps, on_step=lambda t, uu: states.append(uu.clone()),
+                           strategy="t2", preconditioner="gmg", max_newton=8, cg_rtol=1e-3)
+        pick = np.linspace(0, len(states) - 1, min(states_per_path, len(states))).round().astype(int)
+        samples = []
+        for k in pick:
+            op.set_state(states[k])
+            samples.append(Sample(states[k], residuals_at_state(op, cd, rng, n_loads=n_loads)))
+        out.append((lam, samples))
+        if log:
+            log(f"path theta={theta:.1f} lam={lam:.1f}: {len(states)} states, {len(samples)} sampled")
+        op.close()
+    return out
+
+
+def energy_step(op, net, r1, cd, lr=None):
+    """J(N) = N.K N / 2 - N.r1 for the correction N of residual r1 at the
+    operator's state (T2 cache built); with lr, also one Adam step on J."""
+    import torch
+    feat, scale = op.patch_features(r1, variant=net.variant)
+    P = feat.shape[0]
+    act, y, dy, work = net._buf(P)
+    mfe_net_forward(net.w.data_ptr(), feat.data_ptr(), P, act.data_ptr(), y.data_ptr(), net.var)
+    z = torch.zeros_like(r1)
+    op.patch_scatter(y, scale, z)
+    z[cd] = 0.0
+    Kz = op.apply(z, strategy="t2")
+    J = 0.5 * float(torch.dot(z, Kz)) - float(torch.dot(z, r1))
+    if lr is not None:
+        g = Kz - r1
+        op.patch_adjoint(g, scale, dy)
+        mfe_net_backward(net.w.data_ptr(), feat.data_ptr(), act.data_ptr(), dy.data_ptr(), P, work.data_ptr(),
+                         net.g.data_ptr(), net.var)
+        net.step += 1
+        mfe_net_adam(net.w.data_ptr(), net.g.data_ptr(), net.m.data_ptr(), net.v.data_ptr(), net.step, lr)
+    return J
+
+
+def train(data, nx=64, ny=16, nz=16, epochs=10, lr=1e-3, seed=0, device=0, log=None, variant="relu"):
+    """Adam on the energy of the correction over every (state, residual) of
+    `data` (from generate); returns (Net, per-epoch mean J)."""
+    import torch
+    net = Net(init_params(seed), torch.device("cuda", device), variant)
+    rng = np.random.default_rng(seed)
+    hist = []
+    ops = {}
+    for lam, _ in data:
+        if lam not in ops:
+            ops[lam] = beam(nx, ny, nz, lam, device)
+    for ep in range(epochs):
+        tot, cnt = 0.0, 0
+        order = [(li, si) for li, (_, ss) in enumerate(data) for si in range(len(ss))]
+        rng.shuffle(order)
+        for li, si in order:
+            lam, samples = data[li]
+            op, _, cd = ops[lam]
+            smp = samples[si]
+            op.set_state(smp.u)
+            op.build_cache("t2")
+            cdt = torch.from_numpy(np.asarray(cd)).to(op.device)
+            for k in rng.permutation(len(smp.residuals)):
+                tot += energy_step(op, net, smp.residuals[k], cdt, lr)
+                cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: mean J {hist[-1]:.4e}")
+    for op, _, _ in ops.values():
+        op.close()
+    return net, hist
