@@ -190,6 +190,39 @@ def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
     return out
 
 
+# --------------------------------------------------------------------------- split law
+def split_leg(name, steps, warmup) -> dict:
+    """The split neo-Hookean law (mu, kappa = the workload's lambda) through
+    the model-independent strategies, FP64: dual-number on-the-fly and the
+    fourth-order cache (filled from dual-number derivatives)."""
+    import torch
+
+    import paper_2505_15535_amd as mfe
+    import synthetic
+
+    cfg = synthetic.get_config(name)
+    dev = torch.device("cuda", 0)
+    op = mfe.Operator(cfg.nx, cfg.ny, cfg.nz, cfg.degree, cfg.vertices(), cfg.mu, cfg.lam, device=0)
+    op.set_model("split")
+    op.set_state(torch.from_numpy(cfg.displacement()).to(dev))
+    w = torch.from_numpy(cfg.test_vector(0)).to(dev)
+    v = torch.empty_like(w)
+    out = {"workload": cfg.description, "law": "split neo-Hookean, mu=1, kappa=lambda"}
+    for s in ("otf_ad", "t4"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.build_cache(s)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        step_ms, kern_ms = time_applies(op, w, v, s, "fp64", steps, warmup)
+        out[s] = {"ms_per_step": round(step_ms, 5), "kernel_ms": round(kern_ms, 5),
+                  "gdofs": round(op.n_dofs / (step_ms * 1e-3) / 1e9, 4), "cache_build_ms": round(build_ms, 3)}
+        print(f"[bench] split law {s}: {out[s]['gdofs']:.2f} GDoF/s (build {build_ms:.2f} ms)", file=sys.stderr,
+              flush=True)
+    op.close()
+    return out
+
+
 # --------------------------------------------------------------------------- Newton-CG
 NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=8, max_cg=2000, newton_atol=1e-8,
                    cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0)
@@ -296,8 +329,8 @@ def main(argv=None):
     ap.add_argument("--mixed", default="box24_q4,box12_q6",
                     help="workloads of the FP64-vs-FP32 apply comparison (the headline one is added)")
     ap.add_argument("--no-newton", action="store_true")
-    ap.add_argument("--legs", default="apply,mixed,newton,learned",
-                    help="subset of apply,mixed,newton,learned to run (profiling runs; the default runs all)")
+    ap.add_argument("--legs", default="apply,mixed,split,newton,learned",
+                    help="subset of apply,mixed,split,newton,learned to run (profiling runs; the default runs all)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (reference for HBM counters)")
@@ -384,6 +417,8 @@ def main(argv=None):
         if "mixed" in legs:
             line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup)
                              for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
+        if "split" in legs:
+            line["split"] = split_leg(cfg.name, args.steps, args.warmup)
         if "newton" in legs and not args.no_newton:
             line["newton"] = newton_leg()
         if "learned" in legs:
@@ -416,6 +451,8 @@ def main(argv=None):
     if "mixed" in legs:
         line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup)
                          for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
+    if "split" in legs:
+        line["split"] = split_leg(cfg.name, args.steps, args.warmup)
     if "newton" in legs and not args.no_newton:
         line["newton"] = newton_leg()
     if "learned" in legs:

@@ -131,6 +131,20 @@ int64_t mfe_n_qpoints(const mfe_ctx* ctx);
 int mfe_set_material(mfe_ctx* ctx, double mu, double lambda,
                      const double* per_cell_mu_lambda_host);
 
+/* Stored-energy function: MFE_MODEL_NH, the compressible neo-Hookean law of
+ * eq. hypref with (mu, lambda) (the default), or MFE_MODEL_SPLIT, the
+ * isochoric-volumetric split law of eq. hypcomplex,
+ * Psi = mu/2 (J^-2/3 tr C - 3) + kappa/2 ((J^2 - 1)/2 - log J),
+ * whose (mu, kappa) are passed as the (mu, lambda) of mfe_set_material.  The
+ * split law is supported by the strategies that do not depend on the law or
+ * differentiate it with dual numbers -- MFE_OTF_AD and MFE_T4 (whose cache is
+ * filled from dual-number derivatives of P) -- and by mfe_residual and
+ * mfe_energy; MFE_OTF, MFE_OTF_GEOM, MFE_T2, the diagonal and the solver
+ * return MFE_EUNSUPPORTED.  A change of law invalidates the T2/T4 caches. */
+#define MFE_MODEL_NH 0
+#define MFE_MODEL_SPLIT 1
+int mfe_set_model(mfe_ctx* ctx, int model);
+
 /* Homogeneous Dirichlet constraints for the tangent: the listed dofs become
  * identity rows and columns (apply reads w as 0 there and returns v_c = w_c;
  * residual entries there are 0).  dofs_host: host array of n dof indices in

@@ -22,6 +22,7 @@ Modules
 basis     1D Gauss rule, Gauss-Lobatto-Legendre support points, Lagrange basis
 mesh      structured Q_p box: numbering, trilinear geometry, basis gradients
 material  energy, first Piola-Kirchhoff stress, explicit tangent tensor
+material_split  the same for the split (isochoric-volumetric) neo-Hookean law
 fem       state, residual, energy, assembled tangent, naive apply
 linelast  textbook small-strain stiffness B^T D B (pin for the u = 0 limit)
 solver    Newton on the weak form with assembled tangent and direct solves
@@ -32,5 +33,5 @@ Every function is float64 unless it is fed complex128 input for the
 complex-step pins, in which case it works in complex128 throughout.
 """
 
-from . import basis, mesh, material, fem, linelast, solver, net  # noqa: F401
+from . import basis, mesh, material, material_split, fem, linelast, solver, net  # noqa: F401
 from .mesh import BoxMesh  # noqa: F401

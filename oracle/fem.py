@@ -24,13 +24,19 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from . import material
+from . import material, material_split
 from .mesh import BoxMesh
 
 
 class Problem:
     def __init__(self, mesh: BoxMesh, mu: float, lam: float, constrained_dofs=None,
-                 elem_mu_lam=None, chunk: int = 1024):
+                 elem_mu_lam=None, chunk: int = 1024, model: str = "nh"):
+        """model "nh": eq. hypref with (mu, lam); "split": eq. hypcomplex with
+        (mu, kappa) passed in the lam slot (and in elem_mu_lam)."""
+        if model not in ("nh", "split"):
+            raise ValueError(f"unknown model {model}")
+        self.model = model
+        self.mat = material if model == "nh" else material_split
         self.mesh = mesh
         self.mu, self.lam = float(mu), float(lam)
         self.chunk = int(chunk)
@@ -76,7 +82,7 @@ class Problem:
             gradN, JxW = self.mesh.geometry(el)
             F = np.eye(3) + np.einsum("eia,eqaA->eqiA", self._local(u, el), gradN)
             mu, lam = self._material(el)
-            total = total + np.sum(JxW * material.energy_density(F, mu, lam))
+            total = total + np.sum(JxW * self.mat.energy_density(F, mu, lam))
         return total
 
     def residual(self, u):
@@ -85,7 +91,7 @@ class Problem:
             gradN, JxW = self.mesh.geometry(el)
             F = np.eye(3) + np.einsum("eia,eqaA->eqiA", self._local(u, el), gradN)
             mu, lam = self._material(el)
-            P = material.piola(F, mu, lam)
+            P = self.mat.piola(F, mu, lam)
             Re = np.einsum("eq,eqiA,eqaA->eia", JxW, P, gradN)
             np.add.at(R, self.mesh.elem_dofs(el).ravel(), Re.ravel())
         R[self.constrained] = 0.0
@@ -103,7 +109,7 @@ class Problem:
             gradN, JxW = self.mesh.geometry(el)
             F = np.eye(3) + np.einsum("eia,eqaA->eqiA", self._local(u, el), gradN)
             mu, lam = self._material(el)
-            L = material.tangent(F, mu, lam)                                  # [E,q,3,3,3,3]
+            L = self.mat.tangent(F, mu, lam)                                  # [E,q,3,3,3,3]
             H = np.einsum("eja,eqaB->eqjB", self._local(w0, el), gradN)      # Grad w
             G = np.einsum("eqiAjB,eqjB->eqiA", L, H)                          # L : Grad w
             ve = np.einsum("eq,eqiA,eqaA->eia", JxW, G, gradN)
@@ -129,7 +135,7 @@ class Problem:
         el = np.arange(self.mesh.n_elems) if elems is None else np.asarray(elems)
         F = np.eye(3) + np.einsum("eia,eqaA->eqiA", self._local(u, el), gradN)
         mu, lam = self._material(el)
-        L = material.tangent(F, mu, lam)
+        L = self.mat.tangent(F, mu, lam)
         return np.einsum("eq,eqaA,eqiAjB,eqbB->eiajb", JxW, gradN, L, gradN, optimize=True)
 
     def assemble_tangent(self, u) -> sp.csr_matrix:

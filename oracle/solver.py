@@ -30,7 +30,8 @@ def newton(problem: Problem, u0, dirichlet_dofs, dirichlet_values, atol=1e-8, ma
     from u0 (whose constrained entries hold the previous Dirichlet values).
     Returns (u, list of ||R|| before each correction and at the end)."""
     u = np.array(u0, dtype=np.float64, copy=True)
-    free_problem = Problem(problem.mesh, problem.mu, problem.lam, elem_mu_lam=problem.elem_mu_lam)
+    free_problem = Problem(problem.mesh, problem.mu, problem.lam, elem_mu_lam=problem.elem_mu_lam,
+                           model=problem.model)
     dg = np.zeros_like(u)
     dg[dirichlet_dofs] = np.asarray(dirichlet_values) - u[dirichlet_dofs]
     hist = []

@@ -82,6 +82,7 @@ _SIGS = {
     "mfe_n_qpoints": (_i64, [_vp]),
     "mfe_set_material": (_i, [_vp, _d, _d, _vp]),
     "mfe_set_constraints": (_i, [_vp, _i64, _vp]),
+    "mfe_set_model": (_i, [_vp, _i]),
     "mfe_set_state": (_i, [_vp, _vp, _vp]),
     "mfe_build_cache": (_i, [_vp, _i, _vp]),
     "mfe_build_cache_fp32": (_i, [_vp, _i, _vp]),
@@ -223,6 +224,14 @@ def mfe_gmg_apply(ctx, opts: SolveOpts, r_dev_ptr, z_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_gmg_apply(ctx, ctypes.byref(opts), r_dev_ptr, z_dev_ptr, stream))
 
 
+MFE_MODEL_NH, MFE_MODEL_SPLIT = 0, 1
+MODELS = {"nh": MFE_MODEL_NH, "split": MFE_MODEL_SPLIT}
+
+
+def mfe_set_model(ctx, model):
+    return _check(ctx, _lib.mfe_set_model(ctx, int(model)))
+
+
 def mfe_set_network(ctx, params_host_ptr, variant=MFE_NET_RELU):
     return _check(ctx, _lib.mfe_set_network(ctx, params_host_ptr, int(variant)))
 
@@ -357,6 +366,10 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+    def set_model(self, model):
+        """Stored-energy law: "nh" (eq. hypref, (mu, lambda)) or "split" (eq. hypcomplex, (mu, kappa))."""
+        mfe_set_model(self.ctx, MODELS.get(model, model))
 
     def set_material(self, mu, lam, per_cell=None):
         import numpy as np

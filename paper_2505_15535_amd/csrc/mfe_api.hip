@@ -31,6 +31,12 @@ int cache_slot(int strategy) {
         default: return -1;
     }
 }
+// strategies that do not depend on the law, or that differentiate it with
+// dual numbers, exist for the split law; the closed-form ones are model specific
+bool strategy_supported(int model, int strategy) {
+    return model == MFE_MODEL_NH || strategy == MFE_OTF_AD || strategy == MFE_T4;
+}
+
 int cache_fields(int slot) {
     return slot == 0 ? mfe::kGeomFields : (slot == 1 ? mfe::kT2Fields : mfe::kT4Fields);
 }
@@ -225,7 +231,8 @@ struct mfe_ctx {
     int64_t nq_stride = 0;          // cache entries per field (bricks * points per brick)
     Tables1D tab;
     double* d_verts = nullptr;
-    // material
+    // material: law (MFE_MODEL_*) and its two moduli (mu, lambda) or (mu, kappa)
+    int model = MFE_MODEL_NH;
     double mu = 1.0, lam = 1.0;
     double* d_cellmat = nullptr;
     // constraints
@@ -542,6 +549,21 @@ int mfe_set_material(mfe_ctx* c, double mu, double lam, const double* per_cell) 
     return MFE_OK;
 }
 
+int mfe_set_model(mfe_ctx* c, int model) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (model != MFE_MODEL_NH && model != MFE_MODEL_SPLIT) return fail(c, MFE_EINVAL, "unknown model");
+    if (model != c->model) {
+        DeviceGuard g(c->device);
+        MFE_HIP(c, hipDeviceSynchronize());
+        mg_free(c);
+        c->model = model;
+        c->cache_valid[1] = c->cache_valid[2] = false;  // the law enters T2/T4
+        c->cache32_valid[1] = c->cache32_valid[2] = false;
+    }
+    return MFE_OK;
+}
+
 int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
     if (!c) return MFE_EINVAL;
     c->err.clear();
@@ -602,13 +624,16 @@ int mfe_build_cache(mfe_ctx* c, int strategy, void* stream) {
     if (strategy == MFE_OTF || strategy == MFE_OTF_AD) return MFE_OK;
     const int slot = cache_slot(strategy);
     if (slot < 0) return fail(c, MFE_EINVAL, "unknown strategy");
+    if (slot == 1 && c->model != MFE_MODEL_NH)
+        return fail(c, MFE_EUNSUPPORTED, "the second-order cache is specific to the neo-Hookean law of eq. hypref");
     if (slot > 0 && !c->has_state) return fail(c, MFE_ESTATE, "no state set");
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!c->d_cache[slot]) MFE_HIP(c, hipMalloc(&c->d_cache[slot], (size_t)cache_fields(slot) * c->nq_stride * sizeof(double)));
     KParams p = base_params(c);
     p.cache_out = c->d_cache[slot];
-    const int mode = slot == 0 ? mfe::MODE_BUILD_GEOM : (slot == 1 ? mfe::MODE_BUILD_T2 : mfe::MODE_BUILD_T4);
+    const int t4 = c->model == MFE_MODEL_SPLIT ? mfe::MODE_BUILD_T4_SPLIT : mfe::MODE_BUILD_T4;
+    const int mode = slot == 0 ? mfe::MODE_BUILD_GEOM : (slot == 1 ? mfe::MODE_BUILD_T2 : t4);
     MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s));
     c->cache_valid[slot] = true;
     c->cache_version[slot] = c->state_version;
@@ -623,6 +648,8 @@ int mfe_build_cache_fp32(mfe_ctx* c, int strategy, void* stream) {
     if (strategy == MFE_OTF || strategy == MFE_OTF_AD) return MFE_OK;
     if (slot < 0) return fail(c, MFE_EINVAL, "unknown strategy");
     if (slot == 0) return mfe_build_cache(c, strategy, stream);  // FP32 OTF_GEOM applies read FP64 geometry
+    if (slot == 1 && c->model != MFE_MODEL_NH)
+        return fail(c, MFE_EUNSUPPORTED, "the second-order cache is specific to the neo-Hookean law of eq. hypref");
     if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -630,7 +657,8 @@ int mfe_build_cache_fp32(mfe_ctx* c, int strategy, void* stream) {
         MFE_HIP(c, hipMalloc(&c->d_cache32[slot], (size_t)cache_fields(slot) * c->nq_stride * sizeof(float)));
     KParams p = base_params(c);
     p.cache_out32 = c->d_cache32[slot];
-    MFE_HIP(c, mfe::launch_cell_kernel(slot == 1 ? mfe::MODE_BUILD_T2 : mfe::MODE_BUILD_T4, c->tab, p, s, true));
+    const int t4 = c->model == MFE_MODEL_SPLIT ? mfe::MODE_BUILD_T4_SPLIT : mfe::MODE_BUILD_T4;
+    MFE_HIP(c, mfe::launch_cell_kernel(slot == 1 ? mfe::MODE_BUILD_T2 : t4, c->tab, p, s, true));
     c->cache32_valid[slot] = true;
     c->cache32_version[slot] = c->state_version;
     return MFE_OK;
@@ -663,9 +691,13 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         case MFE_OTF_GEOM: mode = mfe::MODE_APPLY_OTF_GEOM; break;
         case MFE_T2: mode = mfe::MODE_APPLY_T2; break;
         case MFE_T4: mode = mfe::MODE_APPLY_T4; break;
-        case MFE_OTF_AD: mode = mfe::MODE_APPLY_OTF_AD; break;
+        case MFE_OTF_AD:
+            mode = c->model == MFE_MODEL_SPLIT ? mfe::MODE_APPLY_OTF_AD_SPLIT : mfe::MODE_APPLY_OTF_AD;
+            break;
         default: return fail(c, MFE_EINVAL, "unknown strategy");
     }
+    if (!strategy_supported(c->model, strategy))
+        return fail(c, MFE_EUNSUPPORTED, "this strategy is written for the neo-Hookean law of eq. hypref");
     if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
     const int slot = cache_slot(strategy);
     if (slot == 0 || (slot > 0 && !fp32)) {
@@ -745,7 +777,8 @@ int mfe_energy(mfe_ctx* c, const double* u, double* energy, void* stream) {
     KParams p = base_params(c);
     p.u = u;
     p.v = c->d_energy;
-    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_ENERGY, c->tab, p, s));
+    MFE_HIP(c, mfe::launch_cell_kernel(c->model == MFE_MODEL_SPLIT ? mfe::MODE_ENERGY_SPLIT : mfe::MODE_ENERGY,
+                                       c->tab, p, s));
     MFE_HIP(c, mfe::launch_sum(c->d_energy, nb, c->d_energy + nb, s));
     MFE_HIP(c, hipMemcpyAsync(c->h_scalars + 3, c->d_energy + nb, sizeof(double), hipMemcpyDeviceToHost, s));
     MFE_HIP(c, hipStreamSynchronize(s));
@@ -765,7 +798,8 @@ int mfe_residual(mfe_ctx* c, const double* u, double* r, void* stream) {
     p.u = u;
     p.v = r;
     MFE_HIP(c, mfe::launch_fill(r, c->n_dofs, 0.0, s));
-    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_RESIDUAL, c->tab, p, s));
+    MFE_HIP(c, mfe::launch_cell_kernel(c->model == MFE_MODEL_SPLIT ? mfe::MODE_RESIDUAL_SPLIT : mfe::MODE_RESIDUAL,
+                                       c->tab, p, s));
     if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, r, s));
     return MFE_OK;
 }
@@ -804,6 +838,8 @@ int dot2(mfe_ctx* c, const double* a, const double* b, const double* x, const do
 
 int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
     if (!o) return fail(c, MFE_EINVAL, "null options");
+    if (c->model != MFE_MODEL_NH)
+        return fail(c, MFE_EUNSUPPORTED, "the solver (diagonal, smoothers) is built for the law of eq. hypref");
     if (o->strategy < MFE_OTF || o->strategy > MFE_OTF_AD) return fail(c, MFE_EINVAL, "unknown strategy");
     if (o->preconditioner < MFE_PC_NONE || o->preconditioner > MFE_PC_GMG_NET)
         return fail(c, MFE_EINVAL, "unknown preconditioner");
@@ -1693,6 +1729,8 @@ int mfe_diagonal(mfe_ctx* c, double* d, void* stream) {
     if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
     if (!c->has_state) return fail(c, MFE_ESTATE, "no state set");
     if (!d) return fail(c, MFE_EINVAL, "null vector");
+    if (c->model != MFE_MODEL_NH)
+        return fail(c, MFE_EUNSUPPORTED, "the diagonal is built from the second-order cache of eq. hypref");
     DeviceGuard g(c->device);
     int rc = ensure_work(c);
     if (rc != MFE_OK) return rc;

@@ -301,6 +301,163 @@ MFE_HD void pointwise_otf_ad(const double du[3][3], const double dw[3][3], const
 }
 
 // --------------------------------------------------------------------------
+// Split neo-Hookean law (Sec. 3.3, eq. hypcomplex) with bulk modulus kappa:
+//   Psi = mu/2 (J^-2/3 tr C - 3) + kappa/2 ((J^2 - 1)/2 - log J)
+//   P   = a (F - I1/3 F^-T) + b F^-T,   a = mu J^-2/3, b = kappa/2 (J^2 - 1),
+// I1 = tr C.  Its tangent is never written out here: the on-the-fly apply
+// differentiates P with dual numbers (the same "seed" evaluation as for the
+// other law) and the fourth-order cache is filled from nine such directional
+// derivatives -- the model-independent strategies of the paper.
+// --------------------------------------------------------------------------
+MFE_HD Dual dual_pow(Dual a, double e) {
+    const double v = pow(a.v, e);
+    return {v, e * v / a.v * a.d};
+}
+
+MFE_HD void piola_split_dual(const Dual F[3][3], double mu, double kappa, Dual P[3][3]) {
+    Dual c[3][3];  // cofactor matrix: F^-T = c / J
+    c[0][0] = dual_fms(F[1][1], F[2][2], F[1][2], F[2][1]);
+    c[1][0] = dual_fms(F[0][2], F[2][1], F[0][1], F[2][2]);
+    c[2][0] = dual_fms(F[0][1], F[1][2], F[0][2], F[1][1]);
+    c[0][1] = dual_fms(F[1][2], F[2][0], F[1][0], F[2][2]);
+    c[1][1] = dual_fms(F[0][0], F[2][2], F[0][2], F[2][0]);
+    c[2][1] = dual_fms(F[0][2], F[1][0], F[0][0], F[1][2]);
+    c[0][2] = dual_fms(F[1][0], F[2][1], F[1][1], F[2][0]);
+    c[1][2] = dual_fms(F[0][1], F[2][0], F[0][0], F[2][1]);
+    c[2][2] = dual_fms(F[0][0], F[1][1], F[0][1], F[1][0]);
+    const Dual J = F[0][0] * c[0][0] + F[0][1] * c[0][1] + F[0][2] * c[0][2];
+    const Dual rJ = dual_recip(J);
+    Dual I1{0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) I1 = I1 + F[i][A] * F[i][A];
+    const Dual a = mu * dual_pow(J, -2.0 / 3.0);
+    const Dual b = (0.5 * kappa) * (J * J - Dual{1.0, 0.0});
+    const Dual third = (1.0 / 3.0) * I1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+            const Dual G = c[i][A] * rJ;
+            P[i][A] = a * (F[i][A] - third * G) + b * G;
+        }
+}
+
+// dP/dxi along the seed Hw on the split law; returns Q = JxW G Jginv^T
+MFE_HD void pointwise_otf_ad_split(const double du[3][3], const double dw[3][3], const double Jginv[3][3],
+                                   double mu, double kappa, double JxW, double Q[3][3]) {
+    double Hu[3][3], Hw[3][3];
+    matmul3(du, Jginv, Hu);
+    matmul3(dw, Jginv, Hw);
+    Dual F[3][3], P[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) F[i][A] = Dual{Hu[i][A] + (i == A ? 1.0 : 0.0), Hw[i][A]};
+    piola_split_dual(F, mu, kappa, P);
+    double G[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) G[i][A] = JxW * P[i][A].d;
+    matmul3_bt(G, Jginv, Q);
+}
+
+// residual integrand of the split law: Q = JxW P Jginv^T
+MFE_HD void pointwise_piola_split(const double F[3][3], const Kin& k, double mu, double kappa,
+                                  const double Jginv[3][3], double JxW, double Q[3][3]) {
+    double I1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) I1 = fma(F[i][A], F[i][A], I1);
+    const double a = mu * pow(k.J, -2.0 / 3.0);
+    const double b = 0.5 * kappa * (k.J * k.J - 1.0);
+    double P[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+            const double G = k.Finv[A][i];
+            P[i][A] = (a * (F[i][A] - I1 / 3.0 * G) + b * G) * JxW;
+        }
+    matmul3_bt(P, Jginv, Q);
+}
+
+// tau = P F^T = a (b - I1/3 I) + b_vol I of the split law, Voigt, times s
+MFE_HD void kirchhoff_split_voigt(const double F[3][3], const Kin& k, double mu, double kappa, double s,
+                                  double tau[6]) {
+    double bb[3][3];
+    matmul3_bt(F, F, bb);
+    const double I1 = bb[0][0] + bb[1][1] + bb[2][2];
+    const double a = mu * pow(k.J, -2.0 / 3.0);
+    const double bv = 0.5 * kappa * (k.J * k.J - 1.0);
+    tau[0] = s * (a * (bb[0][0] - I1 / 3.0) + bv);
+    tau[1] = s * (a * (bb[1][1] - I1 / 3.0) + bv);
+    tau[2] = s * (a * (bb[2][2] - I1 / 3.0) + bv);
+    tau[3] = s * a * bb[1][2];
+    tau[4] = s * a * bb[0][2];
+    tau[5] = s * a * bb[0][1];
+}
+
+// Voigt matrix of J c * s for the split law from nine dual-number directional
+// derivatives of P: L_iAkB = dP_iA/dF_kB, J c_ijkl = F_jA F_lB L_iAkB - d_ik tau_jl,
+// symmetrised over the minor index pairs and the Voigt transpose.
+MFE_HD void spatial_tangent_split_voigt(const double F[3][3], double mu, double kappa, double s, double D21[21]) {
+    double L[3][3][3][3];  // L[i][A][k][B]
+    double P[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int B = 0; B < 3; ++B) {
+            Dual Fd[3][3], Pd[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int A = 0; A < 3; ++A) Fd[i][A] = Dual{F[i][A], (i == k && A == B) ? 1.0 : 0.0};
+            piola_split_dual(Fd, mu, kappa, Pd);
+            for (int i = 0; i < 3; ++i)
+                for (int A = 0; A < 3; ++A) {
+                    L[i][A][k][B] = Pd[i][A].d;
+                    P[i][A] = Pd[i][A].v;
+                }
+        }
+    double T[3][3];  // tau = P F^T
+    matmul3_bt(P, F, T);
+    auto jc = [&](int i, int j, int k, int l) {
+        double v = 0.0;
+        for (int A = 0; A < 3; ++A)
+            for (int B = 0; B < 3; ++B) v = fma(F[j][A] * F[l][B], L[i][A][k][B], v);
+        return v - (i == k ? T[j][l] : 0.0);
+    };
+    const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};
+    double D[6][6];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+            const int i = vi[r], j = vj[r], k = vi[c], l = vj[c];
+            D[r][c] = 0.25 * (jc(i, j, k, l) + jc(j, i, k, l) + jc(i, j, l, k) + jc(j, i, l, k));
+        }
+    for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c) D21[voigt_packed(r, c)] = 0.5 * (D[r][c] + D[c][r]) * s;
+}
+
+// stored energy density of the two laws
+MFE_HD double energy_nh(const double F[3][3], const Kin& k, double mu, double lam) {
+    double trC = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) trC = fma(F[i][j], F[i][j], trC);
+    return 0.5 * mu * (trC - 3.0 - 2.0 * k.lJ) + lam * k.lJ * k.lJ;
+}
+
+MFE_HD double energy_split(const double F[3][3], const Kin& k, double mu, double kappa) {
+    double I1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) I1 = fma(F[i][j], F[i][j], I1);
+    return 0.5 * mu * (pow(k.J, -2.0 / 3.0) * I1 - 3.0) + 0.5 * kappa * (0.5 * (k.J * k.J - 1.0) - k.lJ);
+}
+
+// --------------------------------------------------------------------------
 // Residual integrand: Q = JxW P Jginv^T with P = mu F + (2 lam log J - mu) F^-T.
 // --------------------------------------------------------------------------
 MFE_HD void pointwise_piola(const double F[3][3], const Kin& k, double mu, double lam,

@@ -387,18 +387,19 @@ __device__ __forceinline__ void inverse3(const double Jg[3][3], double Jinv[3][3
 
 template <int MODE>
 struct ModeInfo {
-    static constexpr bool fwd_u = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM ||
-                                  MODE == MODE_APPLY_OTF_AD || MODE == MODE_RESIDUAL ||
-                                  MODE == MODE_STATE || MODE == MODE_BUILD_T2 || MODE == MODE_BUILD_T4 ||
-                                  MODE == MODE_ENERGY;
-    static constexpr bool fwd_w = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM ||
-                                  MODE == MODE_APPLY_OTF_AD || MODE == MODE_APPLY_T2 ||
-                                  MODE == MODE_APPLY_T4;
-    static constexpr bool backward = fwd_w || MODE == MODE_RESIDUAL;
-    static constexpr bool vertex_geom = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_AD ||
-                                        MODE == MODE_RESIDUAL || MODE == MODE_STATE ||
-                                        MODE == MODE_BUILD_GEOM || MODE == MODE_BUILD_T2 ||
-                                        MODE == MODE_BUILD_T4 || MODE == MODE_ENERGY;
+    static constexpr bool split = MODE == MODE_APPLY_OTF_AD_SPLIT || MODE == MODE_RESIDUAL_SPLIT ||
+                                  MODE == MODE_BUILD_T4_SPLIT || MODE == MODE_ENERGY_SPLIT;
+    static constexpr bool otf_ad = MODE == MODE_APPLY_OTF_AD || MODE == MODE_APPLY_OTF_AD_SPLIT;
+    static constexpr bool residual = MODE == MODE_RESIDUAL || MODE == MODE_RESIDUAL_SPLIT;
+    static constexpr bool build_t4 = MODE == MODE_BUILD_T4 || MODE == MODE_BUILD_T4_SPLIT;
+    static constexpr bool energy = MODE == MODE_ENERGY || MODE == MODE_ENERGY_SPLIT;
+    static constexpr bool fwd_u = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || otf_ad || residual ||
+                                  MODE == MODE_STATE || MODE == MODE_BUILD_T2 || build_t4 || energy;
+    static constexpr bool fwd_w = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || otf_ad ||
+                                  MODE == MODE_APPLY_T2 || MODE == MODE_APPLY_T4;
+    static constexpr bool backward = fwd_w || residual;
+    static constexpr bool vertex_geom = MODE == MODE_APPLY_OTF || otf_ad || residual || MODE == MODE_STATE ||
+                                        MODE == MODE_BUILD_GEOM || MODE == MODE_BUILD_T2 || build_t4 || energy;
     static constexpr int cache_fields = MODE == MODE_APPLY_OTF_GEOM ? kGeomFields
                                       : MODE == MODE_APPLY_T2       ? kT2Fields
                                       : MODE == MODE_APPLY_T4       ? kT4Fields
@@ -457,7 +458,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
     // contiguous block, field f of this thread's point at cidx(f)
     constexpr int CF = MODE == MODE_BUILD_GEOM ? kGeomFields
                      : MODE == MODE_BUILD_T2   ? kT2Fields
-                     : MODE == MODE_BUILD_T4   ? kT4Fields
+                     : MI::build_t4            ? kT4Fields
                                                : (MI::cache_fields > 0 ? MI::cache_fields : 1);
     const int64_t cbase = (int64_t)bp.brick * CF * G::NQ + tid;
     auto cidx = [&](int f) { return cbase + (int64_t)f * G::NQ; };
@@ -543,7 +544,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
                 inverse3(Jg, Jinv, det);
                 JxW = det * T.qw[qx] * T.qw[qy] * T.qw[qz];
             }
-            if constexpr (MODE != MODE_APPLY_OTF_AD) kinematics(du, Jinv, F, kin);
+            if constexpr (!MI::otf_ad) kinematics(du, Jinv, F, kin);
         }
     }
 
@@ -552,19 +553,12 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         return;
     }
 
-    if constexpr (MODE == MODE_ENERGY) {
-        // stored energy of the compressible neo-Hookean law, summed over the
-        // brick's points in a fixed order (one partial per brick)
+    if constexpr (MI::energy) {
+        // stored energy of the law, summed over the brick's points in a fixed
+        // order (one partial per brick)
         __shared__ double sRed[G::NT / 64];
         double e = 0.0;
-        if (active) {
-            double trC = 0.0;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) trC = fma(F[i][j], F[i][j], trC);
-            e = (0.5 * mu * (trC - 3.0 - 2.0 * kin.lJ) + lam * kin.lJ * kin.lJ) * JxW;
-        }
+        if (active) e = (MI::split ? energy_split(F, kin, mu, lam) : energy_nh(F, kin, mu, lam)) * JxW;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
         if ((tid & 63) == 0) sRed[tid >> 6] = e;
@@ -577,12 +571,13 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         return;
     }
 
-    if constexpr (MODE == MODE_BUILD_T2 || MODE == MODE_BUILD_T4) {
+    if constexpr (MODE == MODE_BUILD_T2 || MI::build_t4) {
         if (active) {
             R* out = cache_out_of<R>(p);
             double M[3][3], tau[6];
             spatial_map(Jinv, kin, M);
-            kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
+            if constexpr (MI::split) kirchhoff_split_voigt(F, kin, mu, lam, JxW, tau);
+            else kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
             if constexpr (MODE == MODE_BUILD_T2) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) out[cidx(i)] = (R)M[i / 3][i % 3];
@@ -592,7 +587,8 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
                 out[cidx(16)] = (R)(2.0 * (mu - 2.0 * lam * kin.lJ) * JxW);
             } else {
                 double D21[21];
-                spatial_tangent_voigt(kin, mu, lam, JxW, D21);
+                if constexpr (MI::split) spatial_tangent_split_voigt(F, mu, lam, JxW, D21);
+                else spatial_tangent_voigt(kin, mu, lam, JxW, D21);
 #pragma unroll
                 for (int i = 0; i < 21; ++i) out[cidx(i)] = (R)D21[i];
 #pragma unroll
@@ -617,7 +613,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         if (active) {
             R dwr[3][3];
             load_slots<N>(gW, tid, dwr);
-            if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || MODE == MODE_APPLY_OTF_AD) {
+            if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || MI::otf_ad) {
                 // the point-wise response is evaluated in FP64
                 double dw[3][3], Qd[3][3];
 #pragma unroll
@@ -625,6 +621,8 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
 #pragma unroll
                     for (int j = 0; j < 3; ++j) dw[i][j] = dwr[i][j];
                 if constexpr (MODE == MODE_APPLY_OTF_AD) pointwise_otf_ad(du, dw, Jinv, mu, lam, JxW, Qd);
+                else if constexpr (MODE == MODE_APPLY_OTF_AD_SPLIT)
+                    pointwise_otf_ad_split(du, dw, Jinv, mu, lam, JxW, Qd);
                 else pointwise_otf(dw, Jinv, kin, mu, lam, JxW, Qd);
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -640,9 +638,12 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
                 pointwise_t4(dwr, M, cf, tau, Q);
             }
         }
-    } else if constexpr (MODE == MODE_RESIDUAL) {
+    } else if constexpr (MI::residual) {
         static_assert(std::is_same_v<R, double>, "the residual is FP64 only");
-        if (active) pointwise_piola(F, kin, mu, lam, Jinv, JxW, Q);
+        if (active) {
+            if constexpr (MI::split) pointwise_piola_split(F, kin, mu, lam, Jinv, JxW, Q);
+            else pointwise_piola(F, kin, mu, lam, Jinv, JxW, Q);
+        }
     }
 
     if constexpr (MI::backward) {
@@ -797,6 +798,8 @@ static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams
             case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float>(T, p, s);
             case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, float>(T, p, s);
             case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, float>(T, p, s);
+            case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float>(T, p, s);
+            case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, float>(T, p, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -812,6 +815,10 @@ static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams
         case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, double>(T, p, s);
         case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, double>(T, p, s);
         case MODE_ENERGY: return launch_nm<N, MODE_ENERGY, double>(T, p, s);
+        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, double>(T, p, s);
+        case MODE_RESIDUAL_SPLIT: return launch_nm<N, MODE_RESIDUAL_SPLIT, double>(T, p, s);
+        case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, double>(T, p, s);
+        case MODE_ENERGY_SPLIT: return launch_nm<N, MODE_ENERGY_SPLIT, double>(T, p, s);
         default: return hipErrorInvalidValue;
     }
 }

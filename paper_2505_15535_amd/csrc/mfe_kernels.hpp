@@ -19,7 +19,12 @@ enum Mode : int {
     MODE_BUILD_T2 = 8,        // cache <- (M, tau JxW, c1, c2)
     MODE_BUILD_T4 = 9,        // cache <- (Jc JxW, tau JxW, M)
     MODE_ENERGY = 10,         // v[brick] <- sum over the brick's points of JxW psi(F)
-    MODE_COUNT = 11
+    // the split neo-Hookean law (mu, kappa); the other modes do not depend on it
+    MODE_APPLY_OTF_AD_SPLIT = 11,
+    MODE_RESIDUAL_SPLIT = 12,
+    MODE_BUILD_T4_SPLIT = 13,
+    MODE_ENERGY_SPLIT = 14,
+    MODE_COUNT = 15
 };
 
 // Doubles per quadrature point of each cache.
