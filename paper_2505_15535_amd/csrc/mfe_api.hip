@@ -1091,14 +1091,21 @@ int ensure_mg32(mfe_ctx* c) {
 
 // out = M_z M_y M_x in for per-axis matrices M (out nodes m[], in nodes n[]),
 // through the two scratch arrays t1, t2 (each at least m_x n_y n_z, m_x m_y n_z)
+// Fused forms (V-cycle): with rb, the input is read as the free residual
+// (dinv != 0) ? rb - in : 0; with x_add, the result is added to x_add where
+// dinv_out != 0 and `clear` is zeroed (out is not written).
 template <typename T>
-int tensor_apply(mfe_ctx* c, const DevCSR* M, const T* in, T* t1, T* t2, T* out, hipStream_t s) {
+int tensor_apply(mfe_ctx* c, const DevCSR* M, const T* in, T* t1, T* t2, T* out, hipStream_t s,
+                 const T* rb = nullptr, const T* dinv_in = nullptr, T* x_add = nullptr, const T* dinv_out = nullptr,
+                 T* clear = nullptr) {
     const int mx = M[0].rows, my = M[1].rows, mz = M[2].rows;
     const int nx = M[0].cols, ny = M[1].cols, nz = M[2].cols;
     T* tag = nullptr;
-    MFE_HIP(c, mfe::launch_axis_csr(M[0].rowptr, M[0].col, M[0].vals(tag), 0, mx, ny, nz, nx, ny, in, t1, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[0].rowptr, M[0].col, M[0].vals(tag), 0, mx, ny, nz, nx, ny, in, t1, s, rb,
+                                    dinv_in));
     MFE_HIP(c, mfe::launch_axis_csr(M[1].rowptr, M[1].col, M[1].vals(tag), 1, mx, my, nz, mx, ny, t1, t2, s));
-    MFE_HIP(c, mfe::launch_axis_csr(M[2].rowptr, M[2].col, M[2].vals(tag), 2, mx, my, mz, mx, my, t2, out, s));
+    MFE_HIP(c, mfe::launch_axis_csr(M[2].rowptr, M[2].col, M[2].vals(tag), 2, mx, my, mz, mx, my, t2, out, s,
+                                    nullptr, dinv_out, x_add, clear));
     return MFE_OK;
 }
 
@@ -1295,9 +1302,8 @@ int chebyshev(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const T* b, T* x,
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     int rc;
-    if (zero_start) {
-        MFE_HIP(c, mfe::launch_fill(x, n, T(0), s));
-        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<T*>(nullptr), V.dinv, T(0), T(1.0 / theta), n, s));
+    if (zero_start) {  // x = d: no separate clearing of x
+        MFE_HIP(c, mfe::launch_cheb(V.d, x, b, static_cast<T*>(nullptr), V.dinv, T(0), T(1.0 / theta), n, s, true));
     } else {
         rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
         if (rc != MFE_OK) return rc;
@@ -1319,26 +1325,24 @@ template <typename T>
 int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipStream_t s) {
     MGLevel& L = c->mg[l];
     MGVec<T>& V = L.vecs(static_cast<T*>(nullptr));
-    mfe_ctx* lc = L.ctx;
     if (l + 1 == c->mg.size()) return chebyshev(c, o, L, b, x, o->coarse_degree, o->coarse_range, true, s);
     int rc = chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, true, s);
     if (rc != MFE_OK) return rc;
-    const int64_t n = lc->n_dofs;
-    // residual b - K x on the free dofs
+    // K x into V.r; the restriction forms the free residual b - K x on the fly
     rc = level_apply(c, o, L, static_cast<const T*>(x), V.r, s);
     if (rc != MFE_OK) return rc;
-    MFE_HIP(c, mfe::launch_axpby(T(1), b, T(-1), V.r, n, s));
-    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, T(0), V.r, s));
     MGLevel& C = c->mg[l + 1];
     MGVec<T>& CV = C.vecs(static_cast<T*>(nullptr));
-    rc = tensor_apply(c, L.R, static_cast<const T*>(V.r), V.tmp1, V.tmp2, CV.b, s);
+    rc = tensor_apply(c, L.R, static_cast<const T*>(V.r), V.tmp1, V.tmp2, CV.b, s, b,
+                      static_cast<const T*>(V.dinv));
     if (rc != MFE_OK) return rc;
     rc = vcycle(c, o, l + 1, static_cast<const T*>(CV.b), CV.x, s);
     if (rc != MFE_OK) return rc;
-    rc = tensor_apply(c, L.P, static_cast<const T*>(CV.x), V.tmp1, V.tmp2, V.r, s);  // prolongated correction
+    // x += prolongated correction on the free dofs; V.r cleared for the smoother
+    rc = tensor_apply(c, L.P, static_cast<const T*>(CV.x), V.tmp1, V.tmp2, static_cast<T*>(nullptr), s,
+                      static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), x,
+                      static_cast<const T*>(V.dinv), V.r);
     if (rc != MFE_OK) return rc;
-    if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, T(0), V.r, s));
-    MFE_HIP(c, mfe::launch_add_clear(x, V.r, n, s));  // x += correction, V.r cleared again
     return chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, false, s);
 }
 

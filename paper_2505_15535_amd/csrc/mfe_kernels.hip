@@ -473,7 +473,9 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
     if constexpr (MI::cache_fields > 0) {
         const CT* cache = cached_r ? (const CT*)cache_of<R>(p) : (const CT*)p.cache;
 #pragma unroll
-        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? cache[cidx(f)] : CT(0);
+        // read once per apply: non-temporal, so the streamed cache does not
+        // evict the gathered and scattered vectors from the caches
+        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? __builtin_nontemporal_load(cache + cidx(f)) : CT(0);
     }
 
     if constexpr (MI::vertex_geom) {

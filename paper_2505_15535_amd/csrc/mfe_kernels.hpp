@@ -116,17 +116,23 @@ hipError_t launch_invert(double* d, int64_t n, int* bad, hipStream_t s, bool abs
 // Multigrid kernels (FP64 and FP32).  out = M in with the 1D CSR matrix M
 // acting along `axis` of nodal arrays [nz][ny][nx][3] (out extents nx_out,
 // ny_out, nz_out; in has nx_in, ny_in and the out extents elsewhere).
+// Fused forms: with rb, `in` is read as (dinv != 0) ? rb - in : 0 (the free
+// residual); with x, the result is added to x where dinv != 0 and `clear` is
+// zeroed instead of writing out.
 hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const double* vals, int axis, int nx_out,
                            int ny_out, int nz_out, int nx_in, int ny_in, const double* in, double* out,
-                           hipStream_t s);
+                           hipStream_t s, const double* rb = nullptr, const double* dinv = nullptr,
+                           double* x = nullptr, double* clear = nullptr);
 hipError_t launch_axis_csr(const int* rowptr, const int* colidx, const float* vals, int axis, int nx_out,
                            int ny_out, int nz_out, int nx_in, int ny_in, const float* in, float* out,
-                           hipStream_t s);
-// d = c1 d + c2 dinv .* (b - Ax);  x += d;  Ax = 0  (Ax null: b; d is not read when c1 = 0)
+                           hipStream_t s, const float* rb = nullptr, const float* dinv = nullptr,
+                           float* x = nullptr, float* clear = nullptr);
+// d = c1 d + c2 dinv .* (b - Ax);  x += d (x = d with x_init);  Ax = 0
+// (Ax null: b; d is not read when c1 = 0)
 hipError_t launch_cheb(double* d, double* x, const double* b, double* Ax, const double* dinv, double c1,
-                       double c2, int64_t n, hipStream_t s);
+                       double c2, int64_t n, hipStream_t s, bool x_init = false);
 hipError_t launch_cheb(float* d, float* x, const float* b, float* Ax, const float* dinv, float c1, float c2,
-                       int64_t n, hipStream_t s);
+                       int64_t n, hipStream_t s, bool x_init = false);
 // x += y;  y = 0
 hipError_t launch_add_clear(double* x, double* y, int64_t n, hipStream_t s);
 hipError_t launch_add_clear(float* x, float* y, int64_t n, hipStream_t s);
