@@ -1178,10 +1178,11 @@ double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) 
     return hi;
 }
 
-// Estimate of lambda_max(D^-1 K) on a level: m steps of Jacobi-preconditioned
-// CG (FP64, second-order cache) from the level's fixed random right-hand
-// side; the CG coefficients give the Lanczos tridiagonal matrix of D^-1 K,
-// whose largest eigenvalue approaches lambda_max from below.
+// Estimate of lambda_max(D^-1 K) on a level: up to 16 steps of Jacobi-
+// preconditioned CG (FP64, second-order cache) from the level's fixed random
+// right-hand side; the CG coefficients give the Lanczos tridiagonal matrix of
+// D^-1 K, whose largest eigenvalue approaches lambda_max from below.  Stops
+// once the estimate changes by less than 0.5% between steps (after 6).
 int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
     const int64_t n = L.ctx->n_dofs;
     const int m = (int)std::min<int64_t>(16, n);
@@ -1216,6 +1217,13 @@ int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
         const double rz_new = c->h_scalars[1];
         if (!(rz_new > 1e-30 * rz)) break;  // invariant subspace found
         const double beta = rz_new / rz;
+        if (k >= 5) {  // converged estimate?
+            std::vector<double> o2(off.begin(), off.end());
+            o2.resize(diag.size() - 1);
+            const double est = tridiag_lmax(diag, o2);
+            if (k > 5 && std::fabs(est - lmax) <= 0.005 * est) break;
+            lmax = est;
+        }
         if (k + 1 < m) off.push_back(std::sqrt(beta) / alpha);
         MFE_HIP(c, mfe::launch_axpby(1.0, z, beta, pv, n, s));
         rz = rz_new;
