@@ -20,7 +20,9 @@ and contracted with full (p+1)^3-term basis gradients, both
 Modules
 -------
 basis     1D Gauss rule, Gauss-Lobatto-Legendre support points, Lagrange basis
-mesh      structured Q_p box: numbering, trilinear geometry, basis gradients
+mesh      Q_p box and general hexahedral meshes: numbering (the canonical
+          order of the library for general meshes), trilinear geometry,
+          basis gradients
 material  energy, first Piola-Kirchhoff stress, explicit tangent tensor
 material_split  the same for the split (isochoric-volumetric) neo-Hookean law
 fem       state, residual, energy, assembled tangent, naive apply
@@ -34,4 +36,4 @@ complex-step pins, in which case it works in complex128 throughout.
 """
 
 from . import basis, mesh, material, material_split, fem, linelast, solver, net  # noqa: F401
-from .mesh import BoxMesh  # noqa: F401
+from .mesh import BoxMesh, HexMesh  # noqa: F401
