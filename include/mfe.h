@@ -117,6 +117,52 @@ const char* mfe_last_error(const mfe_ctx* ctx);
 int mfe_mesh_box(mfe_ctx* ctx, int nx, int ny, int nz, int degree,
                  const double* vertex_xyz_host);
 
+/* Define a general mesh of n_cells degree-`degree` hexahedra (1 <= degree <=
+ * 6) over n_vertices vertices (Sec. 2.2 discretises with Q_p hexahedra; the
+ * cell integrals of Sec. 2.4 run over any such cells, mapped trilinearly from
+ * their 8 vertices).
+ *   vertex_xyz_host      n_vertices*3 doubles (x,y,z interleaved), copied.
+ *   cell_vertices_host   n_cells*8 int32 vertex ids per cell in lexicographic
+ *                        local order: local vertex bx + 2 by + 4 bz sits at
+ *                        reference corner (bx, by, bz); copied.
+ * Nodes follow the canonical numbering, which depends only on vertex ids:
+ *   1. node v < n_vertices is vertex v;
+ *   2. (degree >= 2) each edge, edges sorted by their (lower, higher) vertex
+ *      ids, owns degree-1 nodes, counted from its lower-id end;
+ *   3. each face, faces sorted by their ascending 4-tuple of vertex ids, owns
+ *      (degree-1)^2 nodes, node (s-1) + (degree-1)(t-1), where s counts support
+ *      points from the face's lowest-id vertex o towards the lower-id of o's
+ *      two edge neighbours on the face and t towards the other;
+ *   4. each cell owns (degree-1)^3 interior nodes in its local lexicographic
+ *      order, cells in order.
+ * Node n carries dofs 3n, 3n+1, 3n+2; support points are Gauss-Lobatto.
+ * Errors: MFE_EINVAL for ids out of range, a cell repeating a vertex, a face
+ * shared by more than two cells or by two cells that disagree on its edges,
+ * or a mesh beyond 32-bit indices; MFE_EJACOBIAN if det J_g <= 0 at a
+ * quadrature point.  Every call except the geometric multigrid and the
+ * learned correction (MFE_EUNSUPPORTED: they need a structured box) works on
+ * such a mesh; per-cell material is indexed by the cell's position in
+ * cell_vertices_host.  Cells are processed in the given order, so an order
+ * with neighbours close together keeps the gathers local.  Resets material,
+ * constraints, state and caches.  Synchronous. */
+int mfe_mesh_hex(mfe_ctx* ctx, int64_t n_vertices, const double* vertex_xyz_host, int64_t n_cells,
+                 const int32_t* cell_vertices_host, int degree);
+
+/* The canonical numbering of mfe_mesh_hex without a context or a device
+ * (host only): n_nodes_out receives the node count and, unless it is NULL,
+ * cell_nodes_host (n_cells*(degree+1)^3 int32, caller-owned) the node of
+ * every (cell, local node a = i + (degree+1)(j + (degree+1)k)).  Returns
+ * MFE_EINVAL for the mesh errors listed at mfe_mesh_hex (except the
+ * geometry, which is not looked at) or null arguments. */
+int mfe_hex_numbering(int64_t n_vertices, int64_t n_cells, const int32_t* cell_vertices_host, int degree,
+                      int32_t* cell_nodes_host, int64_t* n_nodes_out);
+
+/* Reference coordinates of every node of the current mesh (box or general):
+ * xyz_host receives n_dofs doubles, node n at (3n, 3n+1, 3n+2): the trilinear
+ * image of the Gauss-Lobatto support point.  Host memory owned by the
+ * caller.  Synchronous; MFE_EINVAL without a mesh. */
+int mfe_node_coordinates(mfe_ctx* ctx, double* xyz_host);
+
 /* Number of dofs of the current mesh, 3 * n_nodes (0 without a mesh). */
 int64_t mfe_n_dofs(const mfe_ctx* ctx);
 
@@ -127,7 +173,8 @@ int64_t mfe_n_qpoints(const mfe_ctx* ctx);
 /* Material of eq. hypref, Psi = mu/2 (tr C - 3 - 2 log J) + lambda log^2 J.
  * per_cell_mu_lambda_host: NULL for the uniform (mu, lambda), else a host
  * array of n_cells*2 doubles (mu, lambda per cell, cell index
- * ex + nx*(ey + ny*ez)), copied.  Invalidates state-derived caches. */
+ * ex + nx*(ey + ny*ez) on a box, the cell's position on a general mesh),
+ * copied.  Invalidates state-derived caches. */
 int mfe_set_material(mfe_ctx* ctx, double mu, double lambda,
                      const double* per_cell_mu_lambda_host);
 

@@ -77,6 +77,9 @@ _SIGS = {
     "mfe_destroy": (None, [_vp]),
     "mfe_last_error": (ctypes.c_char_p, [_vp]),
     "mfe_mesh_box": (_i, [_vp, _i, _i, _i, _i, _vp]),
+    "mfe_mesh_hex": (_i, [_vp, _i64, _vp, _i64, _vp, _i]),
+    "mfe_node_coordinates": (_i, [_vp, _vp]),
+    "mfe_hex_numbering": (_i, [_i64, _i64, _vp, _i, _vp, ctypes.POINTER(_i64)]),
     "mfe_n_dofs": (_i64, [_vp]),
     "mfe_n_cells": (_i64, [_vp]),
     "mfe_n_qpoints": (_i64, [_vp]),
@@ -154,6 +157,29 @@ def _check(ctx, rc):
 
 def mfe_mesh_box(ctx, nx, ny, nz, degree, vertex_xyz_host_ptr):
     return _check(ctx, _lib.mfe_mesh_box(ctx, nx, ny, nz, degree, vertex_xyz_host_ptr))
+
+
+def mfe_mesh_hex(ctx, n_vertices, vertex_xyz_host_ptr, n_cells, cell_vertices_host_ptr, degree):
+    return _check(ctx, _lib.mfe_mesh_hex(ctx, int(n_vertices), vertex_xyz_host_ptr, int(n_cells),
+                                         cell_vertices_host_ptr, int(degree)))
+
+
+def mfe_hex_numbering(cells, degree, n_vertices):
+    """(cell_nodes [n_cells, (degree+1)^3] int32, n_nodes) of the canonical
+    numbering of a general hexahedral mesh (host only, no device needed)."""
+    import numpy as np
+    cv = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 8))
+    out = np.empty((cv.shape[0], (int(degree) + 1) ** 3), dtype=np.int32)
+    n_nodes = _i64(0)
+    rc = _lib.mfe_hex_numbering(int(n_vertices), cv.shape[0], cv.ctypes.data, int(degree), out.ctypes.data,
+                                ctypes.byref(n_nodes))
+    if rc != MFE_OK:
+        raise MfeError(rc, "invalid hexahedral mesh")
+    return out, int(n_nodes.value)
+
+
+def mfe_node_coordinates(ctx, xyz_host_ptr):
+    return _check(ctx, _lib.mfe_node_coordinates(ctx, xyz_host_ptr))
 
 
 def mfe_n_dofs(ctx) -> int:
@@ -338,23 +364,54 @@ def _dev_f64(t, n, name):
 class Operator:
     """A context holding one mesh, material, constraints, state and caches.
 
-    ``Operator(nx, ny, nz, degree, vertices, mu, lam)`` builds the mesh;
-    ``set_state(u)``, ``build_cache(strategy)``, ``apply(w, out, strategy)``
-    and ``residual(u, out)`` queue work on torch's current stream.
+    ``Operator(nx, ny, nz, degree, vertices, mu, lam)`` builds a box mesh,
+    ``Operator.from_hex(vertices, cells, degree, mu, lam)`` a general
+    hexahedral one; ``set_state(u)``, ``build_cache(strategy)``,
+    ``apply(w, out, strategy)`` and ``residual(u, out)`` queue work on torch's
+    current stream.
     """
 
     def __init__(self, nx, ny, nz, degree, vertices, mu=1.0, lam=1.0, per_cell=None, device=None):
         import numpy as np
+        verts = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1))
+        self._open(device)
+        mfe_mesh_box(self.ctx, nx, ny, nz, degree, verts.ctypes.data)
+        self._finish(mu, lam, per_cell)
+
+    @classmethod
+    def from_hex(cls, vertices, cells, degree, mu=1.0, lam=1.0, per_cell=None, device=None):
+        """General hexahedral mesh: vertices [nv, 3], cells [ne, 8] vertex ids
+        in lexicographic local order; nodes in the canonical numbering."""
+        import numpy as np
+        verts = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1, 3))
+        cv = np.ascontiguousarray(np.asarray(cells).reshape(-1, 8))
+        if cv.size and (cv.min() < 0 or cv.max() >= 2 ** 31):
+            raise ValueError("cell vertex ids must fit in int32 and be >= 0")
+        cv = cv.astype(np.int32)
+        self = cls.__new__(cls)
+        self._open(device)
+        mfe_mesh_hex(self.ctx, verts.shape[0], verts.ctypes.data, cv.shape[0], cv.ctypes.data, degree)
+        self._finish(mu, lam, per_cell)
+        return self
+
+    def _open(self, device):
         import torch
         dev = torch.cuda.current_device() if device is None else int(device)
         self.device = torch.device("cuda", dev)
         self.ctx = mfe_create(dev)
-        verts = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1))
-        mfe_mesh_box(self.ctx, nx, ny, nz, degree, verts.ctypes.data)
+
+    def _finish(self, mu, lam, per_cell):
         self.n_dofs = mfe_n_dofs(self.ctx)
         self.n_cells = mfe_n_cells(self.ctx)
         self.n_qpoints = mfe_n_qpoints(self.ctx)
         self.set_material(mu, lam, per_cell)
+
+    def node_coordinates(self):
+        """Reference coordinates [n_nodes, 3] (numpy float64) of the nodes."""
+        import numpy as np
+        out = np.empty(self.n_dofs, dtype=np.float64)
+        mfe_node_coordinates(self.ctx, out.ctypes.data)
+        return out.reshape(-1, 3)
 
     def close(self):
         if getattr(self, "ctx", None):

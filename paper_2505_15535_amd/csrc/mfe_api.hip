@@ -16,6 +16,7 @@
 
 #include "../../include/mfe.h"
 #include "mfe_kernels.hpp"
+#include "mfe_mesh.hpp"
 
 using mfe::KParams;
 using mfe::Tables1D;
@@ -224,6 +225,12 @@ struct mfe_ctx {
     std::string err;
     // mesh
     bool has_mesh = false;
+    // general hexahedral mesh (mfe_mesh_hex): nx = ny = nz = 0, cells gathered
+    // through the cell-node table d_conn, geometry from d_ev
+    bool hex = false;
+    int* d_conn = nullptr;
+    int* d_ev = nullptr;
+    std::vector<int32_t> h_ev, h_conn;
     int nx = 0, ny = 0, nz = 0, degree = 0;
     int Nx = 0, Ny = 0, Nz = 0;
     int64_t n_nodes = 0, n_dofs = 0, ne = 0, nq = 0;
@@ -353,6 +360,11 @@ void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_fcg);
     c->ninv_valid = false;
     dfree(c->d_verts);
+    dfree(c->d_conn);
+    dfree(c->d_ev);
+    c->hex = false;
+    c->h_ev.clear();
+    c->h_conn.clear();
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
     dfree(c->d_cidx);
@@ -384,6 +396,8 @@ KParams base_params(const mfe_ctx* c) {
     p.verts = c->d_verts;
     p.u = c->d_u;
     p.cell_mat = c->d_cellmat;
+    p.conn = c->d_conn;
+    p.ev = c->d_ev;
     p.mu = c->mu;
     p.lam = c->lam;
     p.flag = c->d_flag;
@@ -394,6 +408,73 @@ bool overlaps(const void* a, const void* b, int64_t bytes) {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
     return x < y + bytes && y < x + bytes;
+}
+
+// det J_g > 0 at every Gauss point of the trilinear map of one cell
+int check_cell_geometry(mfe_ctx* c, const double X[8][3], const Tables1D& t, int64_t e) {
+    const int n = t.n;
+    for (int qz = 0; qz < n; ++qz)
+        for (int qy = 0; qy < n; ++qy)
+            for (int qx = 0; qx < n; ++qx) {
+                const double xi[3] = {t.qp[qx], t.qp[qy], t.qp[qz]};
+                double J[3][3] = {};
+                for (int v = 0; v < 8; ++v) {
+                    const int b[3] = {v & 1, (v >> 1) & 1, v >> 2};
+                    double f[3], df[3];
+                    for (int d = 0; d < 3; ++d) {
+                        f[d] = b[d] ? xi[d] : 1.0 - xi[d];
+                        df[d] = b[d] ? 1.0 : -1.0;
+                    }
+                    const double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+                    for (int d = 0; d < 3; ++d)
+                        for (int A = 0; A < 3; ++A) J[d][A] += X[v][d] * g[A];
+                }
+                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                if (!(det > 0.0)) {
+                    char buf[160];
+                    std::snprintf(buf, sizeof(buf), "det J_g = %g <= 0 in cell %lld", det, (long long)e);
+                    return fail(c, MFE_EJACOBIAN, buf);
+                }
+            }
+    return MFE_OK;
+}
+
+// Reference position of every node: the trilinear image of the cell's
+// Gauss-Lobatto support points (cells sharing a node agree on it).
+void node_positions(const mfe_ctx* c, double* xyz) {
+    const int p = c->degree, n = p + 1, n3 = n * n * n;
+    double gll[8];
+    gll_points(p, gll);
+    for (int64_t e = 0; e < c->ne; ++e) {
+        double X[8][3];
+        int64_t ex = 0, ey = 0, ez = 0;
+        if (!c->hex) {
+            ex = e % c->nx;
+            ey = (e / c->nx) % c->ny;
+            ez = e / ((int64_t)c->nx * c->ny);
+        }
+        for (int v = 0; v < 8; ++v) {
+            const int64_t id = c->hex ? c->h_ev[8 * e + v]
+                                      : (ex + (v & 1)) + (int64_t)(c->nx + 1) * ((ey + ((v >> 1) & 1)) +
+                                                                                (int64_t)(c->ny + 1) * (ez + (v >> 2)));
+            for (int d = 0; d < 3; ++d) X[v][d] = c->h_verts[3 * id + d];
+        }
+        for (int a = 0; a < n3; ++a) {
+            const int i = a % n, j = (a / n) % n, k = a / (n * n);
+            const double xi[3] = {gll[i], gll[j], gll[k]};
+            const int64_t node = c->hex ? c->h_conn[e * n3 + a]
+                                        : (p * ex + i) + (int64_t)c->Nx * ((p * ey + j) + (int64_t)c->Ny * (p * ez + k));
+            double x[3] = {0.0, 0.0, 0.0};
+            for (int v = 0; v < 8; ++v) {
+                const double w = ((v & 1) ? xi[0] : 1.0 - xi[0]) * (((v >> 1) & 1) ? xi[1] : 1.0 - xi[1]) *
+                                 ((v >> 2) ? xi[2] : 1.0 - xi[2]);
+                for (int d = 0; d < 3; ++d) x[d] += w * X[v][d];
+            }
+            for (int d = 0; d < 3; ++d) xyz[3 * node + d] = x[d];
+        }
+    }
 }
 
 }  // namespace
@@ -454,7 +535,6 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
     // host-side check of det J_g > 0 at every Gauss point (trilinear map)
     Tables1D t;
     make_tables(degree, t);
-    const int n = degree + 1;
     for (int64_t e = 0; e < ne; ++e) {
         const int ex = (int)(e % nx), ey = (int)((e / nx) % ny), ez = (int)(e / ((int64_t)nx * ny));
         double X[8][3];
@@ -462,31 +542,8 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
             const int64_t id = (ex + (v & 1)) + (int64_t)(nx + 1) * ((ey + ((v >> 1) & 1)) + (int64_t)(ny + 1) * (ez + (v >> 2)));
             for (int d = 0; d < 3; ++d) X[v][d] = vxyz[3 * id + d];
         }
-        for (int qz = 0; qz < n; ++qz)
-            for (int qy = 0; qy < n; ++qy)
-                for (int qx = 0; qx < n; ++qx) {
-                    const double xi[3] = {t.qp[qx], t.qp[qy], t.qp[qz]};
-                    double J[3][3] = {};
-                    for (int v = 0; v < 8; ++v) {
-                        const int b[3] = {v & 1, (v >> 1) & 1, v >> 2};
-                        double f[3], df[3];
-                        for (int d = 0; d < 3; ++d) {
-                            f[d] = b[d] ? xi[d] : 1.0 - xi[d];
-                            df[d] = b[d] ? 1.0 : -1.0;
-                        }
-                        const double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
-                        for (int d = 0; d < 3; ++d)
-                            for (int A = 0; A < 3; ++A) J[d][A] += X[v][d] * g[A];
-                    }
-                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-                    if (!(det > 0.0)) {
-                        char buf[160];
-                        std::snprintf(buf, sizeof(buf), "det J_g = %g <= 0 in cell %lld", det, (long long)e);
-                        return fail(c, MFE_EJACOBIAN, buf);
-                    }
-                }
+        const int rc = check_cell_geometry(c, X, t, e);
+        if (rc != MFE_OK) return rc;
     }
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, MFE_EHIP, "hipSetDevice failed");
@@ -520,6 +577,86 @@ int mfe_mesh_box(mfe_ctx* c, int nx, int ny, int nz, int degree, const double* v
     c->mu = 1.0;
     c->lam = 1.0;
     c->has_mesh = true;
+    return MFE_OK;
+}
+
+int mfe_mesh_hex(mfe_ctx* c, int64_t nv, const double* vxyz, int64_t ne, const int32_t* ev, int degree) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (nv < 8 || ne < 1) return fail(c, MFE_EINVAL, "need at least 8 vertices and one cell");
+    if (degree < 1 || degree > 6) return fail(c, MFE_EINVAL, "degree must be in 1..6");
+    if (!vxyz || !ev) return fail(c, MFE_EINVAL, "vertex or cell array is null");
+    const int n = degree + 1, n3 = n * n * n;
+    if (nv >= ((int64_t)1 << 31) || ne * n3 >= ((int64_t)1 << 31))
+        return fail(c, MFE_EINVAL, "mesh too large for 32-bit indices");
+    std::vector<int32_t> conn;
+    int64_t n_nodes = 0;
+    const std::string bad = mfe::number_hex_nodes(nv, ne, ev, degree, conn, n_nodes);
+    if (!bad.empty()) return fail(c, MFE_EINVAL, bad);
+    Tables1D t;
+    make_tables(degree, t);
+    for (int64_t e = 0; e < ne; ++e) {
+        double X[8][3];
+        for (int v = 0; v < 8; ++v)
+            for (int d = 0; d < 3; ++d) X[v][d] = vxyz[3 * (int64_t)ev[8 * e + v] + d];
+        const int rc = check_cell_geometry(c, X, t, e);
+        if (rc != MFE_OK) return rc;
+    }
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, MFE_EHIP, "hipSetDevice failed");
+    MFE_HIP(c, hipDeviceSynchronize());
+    free_mesh_data(c);
+    MFE_HIP(c, hipMalloc(&c->d_verts, nv * 3 * sizeof(double)));
+    MFE_HIP(c, hipMemcpy(c->d_verts, vxyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_ev, ne * 8 * sizeof(int32_t)));
+    MFE_HIP(c, hipMemcpy(c->d_ev, ev, ne * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_conn, ne * n3 * sizeof(int32_t)));
+    MFE_HIP(c, hipMemcpy(c->d_conn, conn.data(), ne * n3 * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_u, 3 * n_nodes * sizeof(double)));
+    c->h_verts.assign(vxyz, vxyz + nv * 3);
+    c->h_ev.assign(ev, ev + ne * 8);
+    c->h_conn.swap(conn);
+    c->h_cellmat.clear();
+    c->h_cidx.clear();
+    c->hex = true;
+    c->nx = c->ny = c->nz = 0;
+    c->Nx = c->Ny = c->Nz = 0;
+    c->degree = degree;
+    c->n_nodes = n_nodes;
+    c->n_dofs = 3 * n_nodes;
+    c->ne = ne;
+    c->nq = ne * n3;
+    int cells, ppg;
+    mfe::hex_group_shape(n, &cells, &ppg);
+    c->nbx = (int)((ne + cells - 1) / cells);
+    c->nby = c->nbz = 1;
+    c->nq_stride = (int64_t)c->nbx * ppg;
+    c->tab = t;
+    c->mu = 1.0;
+    c->lam = 1.0;
+    c->has_mesh = true;
+    return MFE_OK;
+}
+
+int mfe_hex_numbering(int64_t nv, int64_t ne, const int32_t* ev, int degree, int32_t* cell_nodes,
+                      int64_t* n_nodes_out) {
+    if (!ev || !n_nodes_out || nv < 8 || ne < 1 || degree < 1 || degree > 6) return MFE_EINVAL;
+    const int64_t n = degree + 1;
+    if (nv >= ((int64_t)1 << 31) || ne * n * n * n >= ((int64_t)1 << 31)) return MFE_EINVAL;
+    std::vector<int32_t> conn;
+    int64_t n_nodes = 0;
+    if (!mfe::number_hex_nodes(nv, ne, ev, degree, conn, n_nodes).empty()) return MFE_EINVAL;
+    *n_nodes_out = n_nodes;
+    if (cell_nodes) std::memcpy(cell_nodes, conn.data(), conn.size() * sizeof(int32_t));
+    return MFE_OK;
+}
+
+int mfe_node_coordinates(mfe_ctx* c, double* xyz) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!xyz) return fail(c, MFE_EINVAL, "null output array");
+    node_positions(c, xyz);
     return MFE_OK;
 }
 
@@ -844,6 +981,8 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
     if (o->preconditioner < MFE_PC_NONE || o->preconditioner > MFE_PC_GMG_NET)
         return fail(c, MFE_EINVAL, "unknown preconditioner");
     if (o->preconditioner == MFE_PC_GMG || o->preconditioner == MFE_PC_GMG_NET) {
+        if (c->hex)
+            return fail(c, MFE_EUNSUPPORTED, "geometric multigrid coarsens structured boxes only (mfe_mesh_box)");
         if (o->mg_levels < 0) return fail(c, MFE_EINVAL, "mg_levels must be >= 0");
         if (o->cheb_degree < 1 || o->coarse_degree < 1) return fail(c, MFE_EINVAL, "Chebyshev degrees must be >= 1");
         if (!(o->cheb_range > 1.0) || !(o->coarse_range > 1.0) || !std::isfinite(o->cheb_range) ||
@@ -1420,7 +1559,7 @@ constexpr int64_t kPatchVox = 729;
 
 int patch_dims(const mfe_ctx* c, int& npx, int& npy, int& npz) {
     npx = npy = npz = 0;
-    if (!c->has_mesh || c->degree != 2 || c->nx % 4 || c->ny % 4 || c->nz % 4) return 0;
+    if (!c->has_mesh || c->hex || c->degree != 2 || c->nx % 4 || c->ny % 4 || c->nz % 4) return 0;
     npx = c->nx / 4;
     npy = c->ny / 4;
     npz = c->nz / 4;

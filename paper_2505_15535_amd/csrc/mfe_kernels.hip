@@ -1,829 +1,10 @@
-// Cell kernels of the matrix-free tangent, residual, state check and cache
-// construction on gfx950.  Every kernel exists in FP64; the tangent applies
-// and the T2/T4 cache builds also exist with FP32 input/output vectors and
-// FP32 sum-factorization sweeps (mixed precision: F, J and log J, the
-// geometry and the cached data are computed in FP64 and rounded once).
-//
-// One workgroup processes a brick of neighbouring cells (4x2x2 for Q2), with
-// one thread per quadrature point of the brick for the point-wise work
-// (Alg. 1/Alg. 2 quadrature loop) and one thread per 1D line of a component
-// for each sum-factorization sweep (Sec. 2.4).  The brick's nodal values are
-// gathered once with coalesced row loads into LDS; intermediate tensors are
-// staged in LDS with workgroup barriers between sweep stages.  The cells'
-// contributions are summed in LDS, then written with plain stores for nodes
-// inside the brick and FP64 atomics for nodes on its faces.  Per-point caches
-// are stored brick-major so that a workgroup streams one contiguous range.
-//
-// Sum factorization (collocation form): nodal values are interpolated to the
-// Gauss points with three sweeps of S (x, y, z), then the reference gradient
-// is taken with the derivative D collocated on the Gauss points; the test
-// contraction applies the transposes in reverse order.
+// Cell kernels on structured boxes (the templates of mfe_cell.hpp
+// instantiated for bricks of neighbouring cells), the launch dispatch between
+// box and general-mesh kernels, and small vector kernels.
 
-#include <type_traits>
-
-#include "mfe_device.hpp"
-#include "mfe_kernels.hpp"
+#include "mfe_cell.hpp"
 
 namespace mfe {
-
-// Bricks: a workgroup owns BX x BY x BZ neighbouring cells of the box.  The
-// Q2 shape can be chosen at build time (cells per direction).
-#ifndef MFE_Q2_BRICK_X
-#define MFE_Q2_BRICK_X 3
-#endif
-#ifndef MFE_Q2_BRICK_Y
-#define MFE_Q2_BRICK_Y 3
-#endif
-#ifndef MFE_Q2_BRICK_Z
-#define MFE_Q2_BRICK_Z 1
-#endif
-template <int N> struct BrickDims;
-template <> struct BrickDims<2> { static constexpr int BX = 4, BY = 4, BZ = 2; };
-template <> struct BrickDims<3> {
-    static constexpr int BX = MFE_Q2_BRICK_X, BY = MFE_Q2_BRICK_Y, BZ = MFE_Q2_BRICK_Z;
-};
-template <> struct BrickDims<4> { static constexpr int BX = 2, BY = 2, BZ = 1; };
-template <> struct BrickDims<5> { static constexpr int BX = 2, BY = 1, BZ = 1; };
-template <> struct BrickDims<6> { static constexpr int BX = 1, BY = 1, BZ = 1; };
-template <> struct BrickDims<7> { static constexpr int BX = 1, BY = 1, BZ = 1; };
-
-template <int N>
-struct Geo {
-    static constexpr int P = N - 1, N2 = N * N, N3 = N2 * N;
-    static constexpr int BX = BrickDims<N>::BX, BY = BrickDims<N>::BY, BZ = BrickDims<N>::BZ;
-    static constexpr int CPB = BX * BY * BZ;               // cells per brick
-    static constexpr int NQ = CPB * N3;                    // quadrature points per brick
-    static constexpr int NT = (NQ + 63) / 64 * 64;         // threads: one per point
-    static constexpr int TASKS = 3 * N2 * CPB;             // 1D lines per sweep stage
-    static constexpr int TPT = (TASKS + NT - 1) / NT;      // lines per thread
-    static constexpr int GX = P * BX + 1, GY = P * BY + 1, GZ = P * BZ + 1;  // brick nodes
-    static constexpr int ROW = 3 * GX;                     // doubles in a brick node row
-    static constexpr int BRICK = ROW * GY * GZ;            // doubles of the brick node array
-    static constexpr int GPT = (BRICK + NT - 1) / NT;      // brick entries per thread
-};
-
-// Map the hardware block index to a brick index so that each of the 8 XCDs
-// (blocks are dealt round-robin to them) works on one contiguous range of
-// bricks and neighbouring bricks share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
-// Position of the workgroup's brick and which of its cells exist.
-struct BrickPos {
-    int brick;
-    int ex0, ey0, ez0;     // first cell
-    int ncx, ncy, ncz;     // existing cells per direction
-    int node0;             // global index of the brick's first node
-};
-
-__device__ __forceinline__ BrickPos brick_pos(const KParams& p, int BX, int BY, int BZ, int P) {
-    BrickPos b;
-    b.brick = xcd_remap(blockIdx.x, gridDim.x);
-    const int bx = b.brick % p.nbx, r = b.brick / p.nbx;
-    const int by = r % p.nby, bz = r / p.nby;
-    b.ex0 = bx * BX;
-    b.ey0 = by * BY;
-    b.ez0 = bz * BZ;
-    b.ncx = min(BX, p.nx - b.ex0);
-    b.ncy = min(BY, p.ny - b.ey0);
-    b.ncz = min(BZ, p.nz - b.ez0);
-    b.node0 = P * b.ex0 + p.Nx * (P * b.ey0 + p.Ny * P * b.ez0);
-    return b;
-}
-
-// One 1D line of a sweep stage: component c, line coordinates (a, b) and
-// brick-local cell lc = lx + BX*(ly + BY*lz).
-struct Line {
-    int c, a, b, lc, lx, ly, lz;
-    bool valid;
-};
-
-template <int N>
-__device__ __forceinline__ Line line_of(int t, const BrickPos& bp) {
-    using G = Geo<N>;
-    Line L;
-    L.c = t % 3;
-    const int r = t / 3;
-    L.a = r % N;
-    L.b = (r / N) % N;
-    L.lc = r / G::N2;
-    L.lx = L.lc % G::BX;
-    L.ly = (L.lc / G::BX) % G::BY;
-    L.lz = L.lc / (G::BX * G::BY);
-    L.valid = t < G::TASKS && L.lx < bp.ncx && L.ly < bp.ncy && L.lz < bp.ncz;
-    return L;
-}
-
-// The brick node array entries handled by this thread: entry
-// e = tid + k*NT is (node row, offset) = (e / ROW, e % ROW) with the x-row of
-// the brick's nodes contiguous, exactly as in the global vector.
-template <int N>
-struct BrickMap {
-    int dof[Geo<N>::GPT];
-    unsigned exists;   // bit k: entry k is a node of an existing cell
-    unsigned face;     // bit k: that node lies on a face of the brick
-};
-
-template <int N>
-__device__ __forceinline__ BrickMap<N> brick_map(const KParams& p, const BrickPos& bp) {
-    using G = Geo<N>;
-    BrickMap<N> m;
-    m.exists = 0u;
-    m.face = 0u;
-#pragma unroll
-    for (int k = 0; k < G::GPT; ++k) {
-        const int e = threadIdx.x + k * G::NT;
-        const int row = e / G::ROW;
-        const int off = e - row * G::ROW;
-        const int jr = row % G::GY, kr = row / G::GY;
-        const int i = off / 3;
-        const bool ex = e < G::BRICK && i <= G::P * bp.ncx && jr <= G::P * bp.ncy && kr <= G::P * bp.ncz;
-        m.dof[k] = 3 * (bp.node0 + p.Nx * (jr + p.Ny * kr)) + off;
-        if (ex) m.exists |= 1u << k;
-        if (i == 0 || i == G::GX - 1 || jr == 0 || jr == G::GY - 1 || kr == 0 || kr == G::GZ - 1)
-            m.face |= 1u << k;
-    }
-    return m;
-}
-
-template <int N, typename R>
-__device__ __forceinline__ void brick_load(const R* __restrict__ src, const BrickMap<N>& m,
-                                           R (&r)[Geo<N>::GPT]) {
-#pragma unroll
-    for (int k = 0; k < Geo<N>::GPT; ++k) r[k] = (m.exists >> k & 1u) ? src[m.dof[k]] : R(0);
-}
-
-template <int N, typename R>
-__device__ __forceinline__ void brick_store(R* sBrick, const R (&r)[Geo<N>::GPT]) {
-#pragma unroll
-    for (int k = 0; k < Geo<N>::GPT; ++k) {
-        const int e = threadIdx.x + k * Geo<N>::NT;
-        if (e < Geo<N>::BRICK) sBrick[e] = r[k];
-    }
-}
-
-// LDS layout.  sG holds 9 doubles per quadrature point, addressed as
-// slot s of component c at point idx of cell lc:  ((lc*N3 + idx)*3 + c)*3 + s.
-// The sweep stages pass their intermediate tensors through the three slots;
-// after the forward sweeps slot d holds d field_c / d xi_d, before the
-// backward sweeps slot d holds Q[c][d].  sV holds 3 doubles per point
-// ((lc*N3 + idx)*3 + c): the values at the Gauss points, then scratch of the
-// backward sweeps.
-template <int N>
-__device__ __forceinline__ int gofs(int lc, int idx, int c) {
-    return ((lc * Geo<N>::N3 + idx) * 3 + c) * 3;
-}
-
-// ---------------------------------------------------------------------------
-// Forward sweeps of one vector field whose brick nodal values are in sBrick
-// (made visible by a barrier before the call).  On exit slot d of sG holds
-// the reference gradient d field_c / d xi_d at every point.
-// ---------------------------------------------------------------------------
-template <int N, typename R>
-__device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<N, R>& T, R* sG, R* sV,
-                                               R* sBrick, bool clear_brick) {
-    using G = Geo<N>;
-    constexpr int N2 = G::N2, P = G::P;
-    // x: interpolate every cell's node x-rows -> slot 0 at (qx, j, k)
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int j = L.a, k = L.b;
-        const R* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
-        R x[N], y[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = row[3 * i];
-        apply_eo<N, false>(T.S, x, y);
-        R* out = sG + gofs<N>(L.lc, N * (j + N * k), L.c);
-#pragma unroll
-        for (int qx = 0; qx < N; ++qx) out[9 * qx] = y[qx];
-    }
-    __syncthreads();
-    // the brick array is free again: clear it for the backward accumulation
-    if (clear_brick)
-        for (int e = threadIdx.x; e < G::BRICK; e += G::NT) sBrick[e] = R(0);
-    // y: slot 0 at (qx, j, k) -> slot 1 at (qx, qy, k)
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-        R x[N], y[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) x[j] = sG[base + 9 * N * j];
-        apply_eo<N, false>(T.S, x, y);
-#pragma unroll
-        for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
-    }
-    __syncthreads();
-    // z: slot 1 -> values at the Gauss points (sV) and their z-derivative (slot 2)
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
-        R x[N], y[N], dz[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) x[k] = sG[base + 9 * N2 * k + 1];
-        apply_eo<N, false>(T.S, x, y);
-        apply_eo<N, true>(T.D, y, dz);
-#pragma unroll
-        for (int qz = 0; qz < N; ++qz) {
-            sV[(base + 9 * N2 * qz) / 3] = y[qz];
-            sG[base + 9 * N2 * qz + 2] = dz[qz];
-        }
-    }
-    __syncthreads();
-    // x- and y-derivatives of the values -> slots 0 and 1
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        {   // x-line at (qy, qz) = (a, b)
-            const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
-            R x[N], y[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * l) / 3];
-            apply_eo<N, true>(T.D, x, y);
-#pragma unroll
-            for (int qx = 0; qx < N; ++qx) sG[base + 9 * qx] = y[qx];
-        }
-        {   // y-line at (qx, qz) = (a, b)
-            const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-            R x[N], y[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sV[(base + 9 * N * l) / 3];
-            apply_eo<N, true>(T.D, x, y);
-#pragma unroll
-            for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
-        }
-    }
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Backward sweeps: on entry slot d of sG holds Q[c][d] at every point (made
-// visible by a barrier) and sBrick is zero.  Adds
-// sum_q sum_d Q[c][d](q) dN_a/dxi_d(q) of every cell to dst.  The cells'
-// contributions are summed in LDS; nodes inside the brick are then written
-// with plain stores, nodes on its faces (shared with neighbouring bricks)
-// with FP64 atomics.
-// ---------------------------------------------------------------------------
-template <int N, typename R>
-__device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const BrickPos& bp, const BrickMap<N>& bm,
-                                                const Tables<N, R>& T, R* sG, R* sV, R* sBrick) {
-    using G = Geo<N>;
-    constexpr int N2 = G::N2, P = G::P;
-    // transposed x- and y-derivatives, in place in slots 0 and 1
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        {
-            const int base = gofs<N>(L.lc, N * (L.a + N * L.b), L.c);
-            R x[N], y[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * l];
-            apply_eo<N, true>(T.Dt, x, y);
-#pragma unroll
-            for (int qx = 0; qx < N; ++qx) sG[base + 9 * qx] = y[qx];
-        }
-        {
-            const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-            R x[N], y[N];
-#pragma unroll
-            for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N * l + 1];
-            apply_eo<N, true>(T.Dt, x, y);
-#pragma unroll
-            for (int qy = 0; qy < N; ++qy) sG[base + 9 * N * qy + 1] = y[qy];
-        }
-    }
-    __syncthreads();
-    // transposed z-derivative, sum of the three directions, transposed
-    // z-interpolation -> sV at (qx, qy, k)
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int base = gofs<N>(L.lc, L.a + N * L.b, L.c);
-        R x[N], y[N], z[N];
-#pragma unroll
-        for (int l = 0; l < N; ++l) x[l] = sG[base + 9 * N2 * l + 2];
-        apply_eo<N, true>(T.Dt, x, y);
-#pragma unroll
-        for (int qz = 0; qz < N; ++qz) y[qz] += sG[base + 9 * N2 * qz] + sG[base + 9 * N2 * qz + 1];
-        apply_eo<N, false>(T.St, y, z);
-#pragma unroll
-        for (int k = 0; k < N; ++k) sV[(base + 9 * N2 * k) / 3] = z[k];
-    }
-    __syncthreads();
-    // transposed y-interpolation: sV at (qx, qy, k) -> slot 0 at (qx, j, k)
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int base = gofs<N>(L.lc, L.a + N2 * L.b, L.c);
-        R x[N], y[N];
-#pragma unroll
-        for (int qy = 0; qy < N; ++qy) x[qy] = sV[(base + 9 * N * qy) / 3];
-        apply_eo<N, false>(T.St, x, y);
-#pragma unroll
-        for (int j = 0; j < N; ++j) sG[base + 9 * N * j] = y[j];
-    }
-    __syncthreads();
-    // transposed x-interpolation, summed into the brick's nodes in LDS
-#pragma unroll
-    for (int it = 0; it < G::TPT; ++it) {
-        const Line L = line_of<N>(threadIdx.x + it * G::NT, bp);
-        if (!L.valid) continue;
-        const int j = L.a, k = L.b;
-        const int base = gofs<N>(L.lc, N * (j + N * k), L.c);
-        R x[N], y[N];
-#pragma unroll
-        for (int qx = 0; qx < N; ++qx) x[qx] = sG[base + 9 * qx];
-        apply_eo<N, false>(T.St, x, y);
-        R* row = sBrick + ((P * L.lz + k) * G::GY + (P * L.ly + j)) * G::ROW + 3 * P * L.lx + L.c;
-#pragma unroll
-        for (int i = 0; i < N; ++i) atomicAdd(row + 3 * i, y[i]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < G::GPT; ++k) {
-        if (!(bm.exists >> k & 1u)) continue;
-        const R val = sBrick[threadIdx.x + k * G::NT];
-        if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
-        else dst[bm.dof[k]] = val;
-    }
-}
-
-template <int N, typename R>
-__device__ __forceinline__ void load_slots(const R* sG, int tid, R g[3][3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g[c][d] = sG[(tid * 3 + c) * 3 + d];
-}
-
-template <int N, typename R>
-__device__ __forceinline__ void store_slots(R* sG, int tid, const R g[3][3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) sG[(tid * 3 + c) * 3 + d] = g[c][d];
-}
-
-__device__ __forceinline__ void inverse3(const double Jg[3][3], double Jinv[3][3], double& det) {
-    double adj[3][3];
-    det = adj_det3(Jg, adj);
-    const double r = 1.0 / det;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Jinv[i][j] = adj[i][j] * r;
-}
-
-template <int MODE>
-struct ModeInfo {
-    static constexpr bool split = MODE == MODE_APPLY_OTF_AD_SPLIT || MODE == MODE_RESIDUAL_SPLIT ||
-                                  MODE == MODE_BUILD_T4_SPLIT || MODE == MODE_ENERGY_SPLIT;
-    static constexpr bool otf_ad = MODE == MODE_APPLY_OTF_AD || MODE == MODE_APPLY_OTF_AD_SPLIT;
-    static constexpr bool residual = MODE == MODE_RESIDUAL || MODE == MODE_RESIDUAL_SPLIT;
-    static constexpr bool build_t4 = MODE == MODE_BUILD_T4 || MODE == MODE_BUILD_T4_SPLIT;
-    static constexpr bool energy = MODE == MODE_ENERGY || MODE == MODE_ENERGY_SPLIT;
-    static constexpr bool fwd_u = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || otf_ad || residual ||
-                                  MODE == MODE_STATE || MODE == MODE_BUILD_T2 || build_t4 || energy;
-    static constexpr bool fwd_w = MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || otf_ad ||
-                                  MODE == MODE_APPLY_T2 || MODE == MODE_APPLY_T4;
-    static constexpr bool backward = fwd_w || residual;
-    static constexpr bool vertex_geom = MODE == MODE_APPLY_OTF || otf_ad || residual || MODE == MODE_STATE ||
-                                        MODE == MODE_BUILD_GEOM || MODE == MODE_BUILD_T2 || build_t4 || energy;
-    static constexpr int cache_fields = MODE == MODE_APPLY_OTF_GEOM ? kGeomFields
-                                      : MODE == MODE_APPLY_T2       ? kT2Fields
-                                      : MODE == MODE_APPLY_T4       ? kT4Fields
-                                                                    : 0;
-};
-
-#ifndef MFE_MIN_WAVES_PER_EU
-#define MFE_MIN_WAVES_PER_EU 1
-#endif
-// Vector and cache element types of a launch: R is the type of w, v, the
-// T2/T4 caches and the sweeps of the w field; the u field, the geometry and
-// the per-point kinematics are always FP64.
-template <typename R>
-__device__ __forceinline__ const R* w_of(const KParams& p) {
-    if constexpr (std::is_same_v<R, float>) return p.w32; else return p.w;
-}
-template <typename R>
-__device__ __forceinline__ R* v_of(const KParams& p) {
-    if constexpr (std::is_same_v<R, float>) return p.v32; else return p.v;
-}
-template <typename R>
-__device__ __forceinline__ const R* cache_of(const KParams& p) {
-    if constexpr (std::is_same_v<R, float>) return p.cache32; else return p.cache;
-}
-template <typename R>
-__device__ __forceinline__ R* cache_out_of(const KParams& p) {
-    if constexpr (std::is_same_v<R, float>) return p.cache_out32; else return p.cache_out;
-}
-
-template <int N, int MODE, typename R>
-__global__ __launch_bounds__(Geo<N>::NT) __attribute__((amdgpu_waves_per_eu(MFE_MIN_WAVES_PER_EU)))
-void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
-    using G = Geo<N>;
-    constexpr int N3 = G::N3;
-    using MI = ModeInfo<MODE>;
-    // LDS element type: FP64 whenever the u field is swept, else R
-    using LT = std::conditional_t<MI::fwd_u, double, R>;
-    // type of the cached per-point data read by an apply
-    constexpr bool cached_r = MODE == MODE_APPLY_T2 || MODE == MODE_APPLY_T4;
-    using CT = std::conditional_t<cached_r, R, double>;
-    __shared__ LT sG[G::NQ * 9];
-    __shared__ LT sV[G::NQ * 3];
-    __shared__ LT sBrick[G::BRICK];
-    __shared__ double sEdge[G::CPB * 36];
-
-    const BrickPos bp = brick_pos(p, G::BX, G::BY, G::BZ, G::P);
-    const BrickMap<N> bm = brick_map<N>(p, bp);
-    const int tid = threadIdx.x;
-    // the quadrature point of this thread
-    const int lc = tid / N3;
-    const int q = tid - lc * N3;
-    const int lx = lc % G::BX, ly = (lc / G::BX) % G::BY, lz = lc / (G::BX * G::BY);
-    const bool active = lc < G::CPB && lx < bp.ncx && ly < bp.ncy && lz < bp.ncz;
-    const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
-    // per-point caches are brick-major: the CF fields of a brick's points are one
-    // contiguous block, field f of this thread's point at cidx(f)
-    constexpr int CF = MODE == MODE_BUILD_GEOM ? kGeomFields
-                     : MODE == MODE_BUILD_T2   ? kT2Fields
-                     : MI::build_t4            ? kT4Fields
-                                               : (MI::cache_fields > 0 ? MI::cache_fields : 1);
-    const int64_t cbase = (int64_t)bp.brick * CF * G::NQ + tid;
-    auto cidx = [&](int f) { return cbase + (int64_t)f * G::NQ; };
-
-    // issue the global loads early: nodal values of the fields, per-point data
-    double ub[G::GPT];
-    R wb[G::GPT];
-    if constexpr (MI::fwd_u) brick_load<N>(p.u, bm, ub);
-    if constexpr (MI::fwd_w) brick_load<N>(w_of<R>(p), bm, wb);
-    constexpr int NCF = MI::cache_fields > 0 ? MI::cache_fields : 1;
-    CT cf[NCF];
-    if constexpr (MI::cache_fields > 0) {
-        const CT* cache = cached_r ? (const CT*)cache_of<R>(p) : (const CT*)p.cache;
-#pragma unroll
-        // read once per apply: non-temporal, so the streamed cache does not
-        // evict the gathered and scattered vectors from the caches
-        for (int f = 0; f < MI::cache_fields; ++f) cf[f] = active ? __builtin_nontemporal_load(cache + cidx(f)) : CT(0);
-    }
-
-    if constexpr (MI::vertex_geom) {
-        // the 12 edge vectors of every cell's trilinear map
-        for (int t = tid; t < G::CPB * 36; t += G::NT) {
-            const int c = t / 36;
-            const int r = t - 36 * c;
-            const int cx = c % G::BX, cy = (c / G::BX) % G::BY, cz = c / (G::BX * G::BY);
-            if (cx >= bp.ncx || cy >= bp.ncy || cz >= bp.ncz) continue;
-            const int edge = r / 3, d = r - 3 * edge;
-            const int dir = edge >> 2, a = edge & 3;
-            int v0;  // edge = 4*dir + a; its end points differ in bit `dir`
-            if (dir == 0) v0 = ((a & 1) << 1) | ((a >> 1) << 2);
-            else if (dir == 1) v0 = (a & 1) | ((a >> 1) << 2);
-            else v0 = (a & 1) | ((a >> 1) << 1);
-            const int v1 = v0 | (1 << dir);
-            const int ex = bp.ex0 + cx, ey = bp.ey0 + cy, ez = bp.ez0 + cz;
-            const int vid0 = (ex + (v0 & 1)) + (p.nx + 1) * ((ey + ((v0 >> 1) & 1)) + (p.ny + 1) * (ez + (v0 >> 2)));
-            const int vid1 = (ex + (v1 & 1)) + (p.nx + 1) * ((ey + ((v1 >> 1) & 1)) + (p.ny + 1) * (ez + (v1 >> 2)));
-            sEdge[t] = p.verts[3 * vid1 + d] - p.verts[3 * vid0 + d];
-        }
-    }
-
-    double mu = p.mu, lam = p.lam;
-    if (p.cell_mat != nullptr && active) {
-        const int cell = (bp.ex0 + lx) + p.nx * ((bp.ey0 + ly) + p.ny * (bp.ez0 + lz));
-        mu = p.cell_mat[2 * cell];
-        lam = p.cell_mat[2 * cell + 1];
-    }
-
-    if constexpr (MODE == MODE_BUILD_GEOM) {
-        __syncthreads();
-        if (active) {
-            double Jg[3][3], Jinv[3][3], det;
-            jacobian_from_edges(sEdge + lc * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
-            inverse3(Jg, Jinv, det);
-            const double JxW = det * T.qw[qx] * T.qw[qy] * T.qw[qz];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) p.cache_out[cidx(3 * i + j)] = Jinv[i][j];
-            p.cache_out[cidx(9)] = JxW;
-        }
-        return;
-    }
-
-    // ---------------- field u: gradients, geometry, kinematics
-    double Jinv[3][3] = {}, JxW = 0.0;
-    Kin kin = {};
-    double F[3][3] = {};
-    double du[3][3] = {};
-    if constexpr (MI::fwd_u) {
-        brick_store<N>(reinterpret_cast<double*>(sBrick), ub);
-        __syncthreads();
-        forward_sweeps<N>(bp, T, reinterpret_cast<double*>(sG), reinterpret_cast<double*>(sV),
-                          reinterpret_cast<double*>(sBrick), !MI::fwd_w);
-        if (active) {
-            load_slots<N>(reinterpret_cast<const double*>(sG), tid, du);
-            if constexpr (MODE == MODE_APPLY_OTF_GEOM) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) Jinv[i][j] = cf[3 * i + j];
-                JxW = cf[9];
-            } else {
-                double Jg[3][3], det;
-                jacobian_from_edges(sEdge + lc * 36, T.qp[qx], T.qp[qy], T.qp[qz], Jg);
-                inverse3(Jg, Jinv, det);
-                JxW = det * T.qw[qx] * T.qw[qy] * T.qw[qz];
-            }
-            if constexpr (!MI::otf_ad) kinematics(du, Jinv, F, kin);
-        }
-    }
-
-    if constexpr (MODE == MODE_STATE) {
-        if (active && !(kin.J > 0.0)) atomicOr(p.flag, 1);
-        return;
-    }
-
-    if constexpr (MI::energy) {
-        // stored energy of the law, summed over the brick's points in a fixed
-        // order (one partial per brick)
-        __shared__ double sRed[G::NT / 64];
-        double e = 0.0;
-        if (active) e = (MI::split ? energy_split(F, kin, mu, lam) : energy_nh(F, kin, mu, lam)) * JxW;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
-        if ((tid & 63) == 0) sRed[tid >> 6] = e;
-        __syncthreads();
-        if (tid == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < G::NT / 64; ++w) sum += sRed[w];
-            p.v[bp.brick] = sum;
-        }
-        return;
-    }
-
-    if constexpr (MODE == MODE_BUILD_T2 || MI::build_t4) {
-        if (active) {
-            R* out = cache_out_of<R>(p);
-            double M[3][3], tau[6];
-            spatial_map(Jinv, kin, M);
-            if constexpr (MI::split) kirchhoff_split_voigt(F, kin, mu, lam, JxW, tau);
-            else kirchhoff_voigt(F, kin, mu, lam, JxW, tau);
-            if constexpr (MODE == MODE_BUILD_T2) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) out[cidx(i)] = (R)M[i / 3][i % 3];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) out[cidx(9 + i)] = (R)tau[i];
-                out[cidx(15)] = (R)(2.0 * lam * JxW);
-                out[cidx(16)] = (R)(2.0 * (mu - 2.0 * lam * kin.lJ) * JxW);
-            } else {
-                double D21[21];
-                if constexpr (MI::split) spatial_tangent_split_voigt(F, mu, lam, JxW, D21);
-                else spatial_tangent_voigt(kin, mu, lam, JxW, D21);
-#pragma unroll
-                for (int i = 0; i < 21; ++i) out[cidx(i)] = (R)D21[i];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) out[cidx(21 + i)] = (R)tau[i];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) out[cidx(27 + i)] = (R)M[i / 3][i % 3];
-            }
-        }
-        return;
-    }
-
-    // ---------------- field w and the point-wise product
-    R* gW = reinterpret_cast<R*>(sG);
-    R* vW = reinterpret_cast<R*>(sV);
-    R* bW = reinterpret_cast<R*>(sBrick);
-    R Q[3][3] = {};
-    if constexpr (MI::fwd_w) {
-        // sBrick was last read before the forward sweeps' first barrier
-        brick_store<N>(bW, wb);
-        __syncthreads();
-        forward_sweeps<N>(bp, TR, gW, vW, bW, true);
-        if (active) {
-            R dwr[3][3];
-            load_slots<N>(gW, tid, dwr);
-            if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || MI::otf_ad) {
-                // the point-wise response is evaluated in FP64
-                double dw[3][3], Qd[3][3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) dw[i][j] = dwr[i][j];
-                if constexpr (MODE == MODE_APPLY_OTF_AD) pointwise_otf_ad(du, dw, Jinv, mu, lam, JxW, Qd);
-                else if constexpr (MODE == MODE_APPLY_OTF_AD_SPLIT)
-                    pointwise_otf_ad_split(du, dw, Jinv, mu, lam, JxW, Qd);
-                else pointwise_otf(dw, Jinv, kin, mu, lam, JxW, Qd);
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) Q[i][j] = (R)Qd[i][j];
-            } else if constexpr (MODE == MODE_APPLY_T2) {
-                const R M[3][3] = {{cf[0], cf[1], cf[2]}, {cf[3], cf[4], cf[5]}, {cf[6], cf[7], cf[8]}};
-                const R tau[6] = {cf[9], cf[10], cf[11], cf[12], cf[13], cf[14]};
-                pointwise_t2(dwr, M, tau, cf[15], cf[16], Q);
-            } else if constexpr (MODE == MODE_APPLY_T4) {
-                const R M[3][3] = {{cf[27], cf[28], cf[29]}, {cf[30], cf[31], cf[32]}, {cf[33], cf[34], cf[35]}};
-                const R tau[6] = {cf[21], cf[22], cf[23], cf[24], cf[25], cf[26]};
-                pointwise_t4(dwr, M, cf, tau, Q);
-            }
-        }
-    } else if constexpr (MI::residual) {
-        static_assert(std::is_same_v<R, double>, "the residual is FP64 only");
-        if (active) {
-            if constexpr (MI::split) pointwise_piola_split(F, kin, mu, lam, Jinv, JxW, Q);
-            else pointwise_piola(F, kin, mu, lam, Jinv, JxW, Q);
-        }
-    }
-
-    if constexpr (MI::backward) {
-        // each thread overwrites only its own point's slots, which only it read
-        if (active) store_slots<N>(gW, tid, Q);
-        __syncthreads();
-        backward_sweeps<N>(v_of<R>(p), bp, bm, TR, gW, vW, bW);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Diagonal of the tangent, for the Jacobi / Chebyshev smoothers of the
-// multigrid-preconditioned CG (Sec. 2.3), from the second-order cache in the
-// current configuration: with g = grad N_a = (dN_a/dxi) M,
-//   K_(a,i),(a,i) = sum_q [ c1 g_i^2 + c2 (|g|^2 + g_i^2) / 2 + g tau g ].
-// One thread per (cell, node) of a brick; contributions of all cells are
-// added with atomics.
-// ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(Geo<N>::NT) void diag_kernel(const KParams p, const DiagTables T,
-                                                          double* __restrict__ diag) {
-    using G = Geo<N>;
-    constexpr int N3 = G::N3, P = G::P;
-    __shared__ double sS[N * N], sSd[N * N];
-    const int tid = threadIdx.x;
-    if (tid < N * N) {
-        sS[tid] = T.S[tid / N][tid % N];
-        sSd[tid] = T.Sd[tid / N][tid % N];
-    }
-    __syncthreads();
-    const BrickPos bp = brick_pos(p, G::BX, G::BY, G::BZ, G::P);
-    const int lc = tid / N3;
-    const int a = tid - lc * N3;
-    const int lx = lc % G::BX, ly = (lc / G::BX) % G::BY, lz = lc / (G::BX * G::BY);
-    if (!(lc < G::CPB && lx < bp.ncx && ly < bp.ncy && lz < bp.ncz)) return;
-    const int i = a % N, j = (a / N) % N, k = a / G::N2;
-    const double* cache = p.cache + (int64_t)bp.brick * kT2Fields * G::NQ + lc * N3;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < N3; ++q) {
-        const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
-        const double Si = sS[qx * N + i], Sj = sS[qy * N + j], Sk = sS[qz * N + k];
-        const double d0 = sSd[qx * N + i] * Sj * Sk;
-        const double d1 = Si * sSd[qy * N + j] * Sk;
-        const double d2 = Si * Sj * sSd[qz * N + k];
-        double M[9], t[6];
-#pragma unroll
-        for (int f = 0; f < 9; ++f) M[f] = cache[f * G::NQ + q];
-#pragma unroll
-        for (int f = 0; f < 6; ++f) t[f] = cache[(9 + f) * G::NQ + q];
-        const double c1 = cache[15 * G::NQ + q], c2 = cache[16 * G::NQ + q];
-        double g[3];
-#pragma unroll
-        for (int n = 0; n < 3; ++n) g[n] = fma(d0, M[n], fma(d1, M[3 + n], d2 * M[6 + n]));
-        const double gg = fma(g[0], g[0], fma(g[1], g[1], g[2] * g[2]));
-        const double gtg = t[0] * g[0] * g[0] + t[1] * g[1] * g[1] + t[2] * g[2] * g[2] +
-                           2.0 * (t[3] * g[1] * g[2] + t[4] * g[0] * g[2] + t[5] * g[0] * g[1]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] += c1 * g[c] * g[c] + 0.5 * c2 * (gg + g[c] * g[c]) + gtg;
-    }
-    const int node = (P * (bp.ex0 + lx) + i) + p.Nx * ((P * (bp.ey0 + ly) + j) + p.Ny * (P * (bp.ez0 + lz) + k));
-#pragma unroll
-    for (int c = 0; c < 3; ++c) unsafeAtomicAdd(diag + 3 * node + c, acc[c]);
-}
-
-// ---------------------------------------------------------------------------
-// Host-side launch
-// ---------------------------------------------------------------------------
-template <int N>
-static void fold(const double A[8][8], bool anti, EO<N>& out) {
-    constexpr int H = EO<N>::H, M = EO<N>::M;
-    for (int q = 0; q < H; ++q)
-        for (int i = 0; i < H; ++i) out.E[q][i] = 0.0;
-    for (int q = 0; q < H; ++q)
-        for (int i = 0; i < (M > 0 ? M : 1); ++i) out.O[q][i] = 0.0;
-    for (int q = 0; q < M; ++q) {
-        for (int i = 0; i < M; ++i) {
-            out.E[q][i] = 0.5 * (A[q][i] + A[q][N - 1 - i]);
-            out.O[q][i] = 0.5 * (A[q][i] - A[q][N - 1 - i]);
-        }
-        if (N % 2 == 1) out.E[q][M] = A[q][M];
-    }
-    if (N % 2 == 1) {
-        if (anti) {
-            for (int i = 0; i < M; ++i) out.O[M][i] = A[M][i];
-        } else {
-            for (int i = 0; i < H; ++i) out.E[M][i] = A[M][i];
-        }
-    }
-}
-
-template <int N>
-static Tables<N> make_tables(const Tables1D& t) {
-    Tables<N> T;
-    double St[8][8], Dt[8][8];
-    for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b) {
-            St[a][b] = t.S[b][a];
-            Dt[a][b] = t.D[b][a];
-        }
-    fold<N>(t.S, false, T.S);
-    fold<N>(St, false, T.St);
-    fold<N>(t.D, true, T.D);
-    fold<N>(Dt, true, T.Dt);
-    for (int i = 0; i < N; ++i) {
-        T.qp[i] = t.qp[i];
-        T.qw[i] = t.qw[i];
-    }
-    return T;
-}
-
-template <int N>
-static Tables<N, float> to_float(const Tables<N>& T) {
-    Tables<N, float> F;
-    auto cvt = [](const EO<N>& a, EO<N, float>& b) {
-        for (int q = 0; q < EO<N>::H; ++q) {
-            for (int i = 0; i < EO<N>::H; ++i) b.E[q][i] = (float)a.E[q][i];
-            for (int i = 0; i < (EO<N>::M > 0 ? EO<N>::M : 1); ++i) b.O[q][i] = (float)a.O[q][i];
-        }
-    };
-    cvt(T.S, F.S);
-    cvt(T.St, F.St);
-    cvt(T.D, F.D);
-    cvt(T.Dt, F.Dt);
-    for (int i = 0; i < N; ++i) {
-        F.qp[i] = T.qp[i];
-        F.qw[i] = T.qw[i];
-    }
-    return F;
-}
-
-template <int N, int MODE, typename R>
-static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream) {
-    const int nb = p.nbx * p.nby * p.nbz;
-    if constexpr (std::is_same_v<R, float>) {
-        const Tables<N, float> TF = to_float<N>(T);
-        hipLaunchKernelGGL((cell_kernel<N, MODE, float>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, TF);
-    } else {
-        hipLaunchKernelGGL((cell_kernel<N, MODE, double>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, T);
-    }
-    return hipGetLastError();
-}
-
-template <int N>
-static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s) {
-    const Tables<N> T = make_tables<N>(t);
-    if (fp32) {
-        switch (mode) {
-            case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float>(T, p, s);
-            case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float>(T, p, s);
-            case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float>(T, p, s);
-            case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float>(T, p, s);
-            case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float>(T, p, s);
-            case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, float>(T, p, s);
-            case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, float>(T, p, s);
-            case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float>(T, p, s);
-            case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, float>(T, p, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (mode) {
-        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, double>(T, p, s);
-        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, double>(T, p, s);
-        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, double>(T, p, s);
-        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, double>(T, p, s);
-        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, double>(T, p, s);
-        case MODE_RESIDUAL: return launch_nm<N, MODE_RESIDUAL, double>(T, p, s);
-        case MODE_STATE: return launch_nm<N, MODE_STATE, double>(T, p, s);
-        case MODE_BUILD_GEOM: return launch_nm<N, MODE_BUILD_GEOM, double>(T, p, s);
-        case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, double>(T, p, s);
-        case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, double>(T, p, s);
-        case MODE_ENERGY: return launch_nm<N, MODE_ENERGY, double>(T, p, s);
-        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, double>(T, p, s);
-        case MODE_RESIDUAL_SPLIT: return launch_nm<N, MODE_RESIDUAL_SPLIT, double>(T, p, s);
-        case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, double>(T, p, s);
-        case MODE_ENERGY_SPLIT: return launch_nm<N, MODE_ENERGY_SPLIT, double>(T, p, s);
-        default: return hipErrorInvalidValue;
-    }
-}
 
 void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick) {
     switch (n) {
@@ -838,43 +19,42 @@ void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick) {
     }
 }
 
-template <int N>
-static hipError_t launch_diag_n(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream) {
-    DiagTables T;
-    for (int a = 0; a < 8; ++a)
-        for (int b = 0; b < 8; ++b) {
-            T.S[a][b] = t.S[a][b];
-            double s = 0.0;  // derivative of the nodal basis at the Gauss points: D S
-            for (int l = 0; l < t.n; ++l) s += t.D[a][l] * t.S[l][b];
-            T.Sd[a][b] = (a < t.n && b < t.n) ? s : 0.0;
-        }
-    const int nb = p.nbx * p.nby * p.nbz;
-    hipLaunchKernelGGL((diag_kernel<N>), dim3(nb), dim3(Geo<N>::NT), 0, stream, p, T, diag);
-    return hipGetLastError();
+void hex_group_shape(int n, int* cells, int* points_per_group) {
+    switch (n) {
+#define MFE_HEX_CASE(K)                                                          \
+    case K:                                                                      \
+        *cells = Geo<K, true>::CPB; *points_per_group = Geo<K, true>::NQ;         \
+        return;
+        MFE_HEX_CASE(2) MFE_HEX_CASE(3) MFE_HEX_CASE(4) MFE_HEX_CASE(5) MFE_HEX_CASE(6) MFE_HEX_CASE(7)
+#undef MFE_HEX_CASE
+        default: *cells = *points_per_group = 0;
+    }
 }
 
 hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream) {
     if (p.ne <= 0) return hipSuccess;
+    if (p.conn) return launch_diagonal_hex(t, p, diag, stream);
     switch (t.n) {
-        case 2: return launch_diag_n<2>(t, p, diag, stream);
-        case 3: return launch_diag_n<3>(t, p, diag, stream);
-        case 4: return launch_diag_n<4>(t, p, diag, stream);
-        case 5: return launch_diag_n<5>(t, p, diag, stream);
-        case 6: return launch_diag_n<6>(t, p, diag, stream);
-        case 7: return launch_diag_n<7>(t, p, diag, stream);
+        case 2: return launch_diag_n<2, false>(t, p, diag, stream);
+        case 3: return launch_diag_n<3, false>(t, p, diag, stream);
+        case 4: return launch_diag_n<4, false>(t, p, diag, stream);
+        case 5: return launch_diag_n<5, false>(t, p, diag, stream);
+        case 6: return launch_diag_n<6, false>(t, p, diag, stream);
+        case 7: return launch_diag_n<7, false>(t, p, diag, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32) {
     if (p.ne <= 0) return hipSuccess;
+    if (p.conn) return launch_cell_kernel_hex(mode, t, p, stream, fp32);
     switch (t.n) {
-        case 2: return launch_n<2>(mode, fp32, t, p, stream);
-        case 3: return launch_n<3>(mode, fp32, t, p, stream);
-        case 4: return launch_n<4>(mode, fp32, t, p, stream);
-        case 5: return launch_n<5>(mode, fp32, t, p, stream);
-        case 6: return launch_n<6>(mode, fp32, t, p, stream);
-        case 7: return launch_n<7>(mode, fp32, t, p, stream);
+        case 2: return launch_n<2, false>(mode, fp32, t, p, stream);
+        case 3: return launch_n<3, false>(mode, fp32, t, p, stream);
+        case 4: return launch_n<4, false>(mode, fp32, t, p, stream);
+        case 5: return launch_n<5, false>(mode, fp32, t, p, stream);
+        case 6: return launch_n<6, false>(mode, fp32, t, p, stream);
+        case 7: return launch_n<7, false>(mode, fp32, t, p, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -49,6 +49,10 @@ struct KParams {
     const float* cache32;      // FP32 T2/T4 applies: cache (OTF_GEOM reads `cache`)
     float* cache_out32;        // FP32 T2/T4 builds: cache written
     const double* cell_mat;    // ne x (mu, lambda) or null
+    // general hexahedral meshes (null for a structured box): global node id of
+    // every (cell, local node), ne x n^3, and the 8 vertex ids of every cell
+    const int* conn;
+    const int* ev;
     double mu, lam;            // uniform material
     int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
 };
@@ -68,11 +72,19 @@ struct Tables1D {
 // n = p+1 points per direction (zeros for an unsupported n).
 void brick_shape(int n, int* bx, int* by, int* bz, int* points_per_brick);
 
+// Cells per workgroup and quadrature points per workgroup of the general-mesh
+// kernels (zeros for an unsupported n); workgroup g owns cells
+// [g*cells, (g+1)*cells).
+void hex_group_shape(int n, int* cells, int* points_per_group);
+
 // Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).  With
 // fp32 the w/v vectors (w32, v32), the T2/T4 caches (cache32, cache_out32)
 // and the sweeps of w are FP32; only the apply and T2/T4 build modes exist so.
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream,
                               bool fp32 = false);
+// The general-mesh instantiations (p.conn != null), reached through
+// launch_cell_kernel and launch_diagonal.
+hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32);
 
 // Nodal basis values S and their derivatives Sd at the Gauss points.
 struct DiagTables {
@@ -83,6 +95,7 @@ struct DiagTables {
 // diag += diagonal of the tangent, from the second-order cache in p.cache
 // (which must be built for the current state).
 hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
+hipError_t launch_diagonal_hex(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
 
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream);
 hipError_t launch_fill(float* x, int64_t n, float value, hipStream_t stream);

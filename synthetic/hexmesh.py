@@ -11,6 +11,9 @@ from __future__ import annotations
 import itertools
 
 import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+from scipy.spatial import cKDTree
 
 
 def box_cells(nx: int, ny: int, nz: int) -> np.ndarray:
@@ -94,28 +97,27 @@ def cube_in_cube(m: int, inner: float = 0.3, jitter: float = 0.0,
                 corners.append(inn(face) if use_inner else outer(face))
             blocks.append(corners)
     t = np.linspace(0.0, 1.0, m + 1)
-    key_of, verts, cells = {}, [], []
-
-    def vid(x):
-        k = tuple(np.round(x, 12))
-        if k not in key_of:
-            key_of[k] = len(verts)
-            verts.append(x)
-        return key_of[k]
-
-    for X in blocks:
-        X = np.array(X)
-        for k in range(m):
-            for j in range(m):
-                for i in range(m):
-                    ids = []
-                    for v in range(8):
-                        s = (t[i + (v & 1)], t[j + ((v >> 1) & 1)], t[k + (v >> 2)])
-                        w = [(s[0] if b & 1 else 1 - s[0]) * (s[1] if b & 2 else 1 - s[1]) *
-                             (s[2] if b & 4 else 1 - s[2]) for b in range(8)]
-                        ids.append(vid(np.einsum("v,vd->d", np.array(w), X)))
-                    cells.append(ids)
-    verts = np.array(verts)
+    s3 = np.stack(np.meshgrid(t, t, t, indexing="ij")[::-1], axis=-1).reshape(-1, 3)   # x fastest
+    bits = np.array([[v & 1, (v >> 1) & 1, v >> 2] for v in range(8)])
+    shape = np.prod(np.where(bits[None, :, :] == 1, s3[:, None, :], 1.0 - s3[:, None, :]), axis=2)
+    pts = np.concatenate([shape @ np.array(X) for X in blocks])          # [7 (m+1)^3, 3]
+    # vertices shared by neighbouring blocks coincide up to rounding: merge
+    # points closer than 1e-9 (the spacing is >= (1 - 2 inner) / m)
+    pairs = cKDTree(pts).query_pairs(1e-9, output_type="ndarray")
+    graph = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(len(pts), len(pts)))
+    _, label = connected_components(graph, directed=False)
+    _, first, ids = np.unique(label, return_index=True, return_inverse=True)
+    order = np.argsort(first)          # number vertices in order of first appearance
+    rank = np.empty_like(order)
+    rank[order] = np.arange(order.size)
+    ids = rank[ids.reshape(-1)]
+    verts = pts[first[order]]
+    kk, jj, ii = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    base = (ii + (m + 1) * (jj + (m + 1) * kk)).reshape(-1)             # cell's (0,0,0) corner
+    off = np.array([bx + (m + 1) * (by + (m + 1) * bz) for bx, by, bz in bits])
+    local = base[:, None] + off[None, :]                                 # [m^3, 8]
+    npb = (m + 1) ** 3
+    cells = np.concatenate([ids[b * npb + local] for b in range(len(blocks))])
     if jitter > 0.0:
         if rng is None:
             raise ValueError("jitter needs a random generator")
