@@ -8,9 +8,11 @@ before the timed region (they are built once per linearisation point; their
 build time is reported separately).  Every strategy is timed; the headline
 `value` is the fastest one.  Beside it, under "mixed": FP64 and FP32-sweep
 applies on the Q4 24^3 and Q6 12^3 boxes (and the headline box) with the
-error of the FP32 result against the FP64 one; under "newton": the twisted
-beam (64x16x16 Q2, lambda/mu = 100, 90 degrees in 10 load steps) solved to
-||R|| <= 1e-8 with GMG-preconditioned CG, FP64 V-cycle and FP32 V-cycle.
+error of the FP32 result against the FP64 one; under "hex": the apply on
+general hexahedral meshes (the headline box given as one, and an unstructured
+mesh of the same size); under "newton": the twisted beam (64x16x16 Q2,
+lambda/mu = 100, 90 degrees in 10 load steps) solved to ||R|| <= 1e-8 with
+GMG-preconditioned CG, FP64 V-cycle and FP32 V-cycle.
 Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box48_q2]
@@ -33,7 +35,8 @@ METRIC = "tangent apply GDoF/s (FP64 vs mixed) + Newton-CG time-to-1e-8 residual
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 STRATEGIES = ["otf", "otf_geom", "t2", "t4", "otf_ad"]
-KERNEL_SOURCES = ["paper_2505_15535_amd/csrc/mfe_kernels.hip", "paper_2505_15535_amd/csrc/mfe_device.hpp"]
+KERNEL_SOURCES = ["paper_2505_15535_amd/csrc/mfe_kernels.hip", "paper_2505_15535_amd/csrc/mfe_kernels_hex.hip",
+                  "paper_2505_15535_amd/csrc/mfe_cell.hpp", "paper_2505_15535_amd/csrc/mfe_device.hpp"]
 
 
 # --------------------------------------------------------------------------- work model
@@ -223,6 +226,72 @@ def split_leg(name, steps, warmup) -> dict:
     return out
 
 
+# --------------------------------------------------------------------------- general meshes
+def hex_model(strategy, degree, n_dofs, n_q, n_vertices, n_cells) -> dict:
+    """work_model plus the index tables a general mesh reads: the int32
+    cell-node table (every apply) and the cell-vertex table (geometry on the
+    fly)."""
+    m = work_model(strategy, degree, n_dofs, n_q, n_vertices)
+    m["index_bytes"] = 4.0 * n_cells * (degree + 1) ** 3 + (32.0 * n_cells if strategy in ("otf", "otf_ad") else 0.0)
+    m["bytes"] += m["index_bytes"]
+    m["intensity"] = m["flops"] / m["bytes"]
+    m["bound"] = "alu" if m["intensity"] > FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) else "hbm"
+    return m
+
+
+def hex_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
+    """The tangent apply on general hexahedral meshes (cells gathered through
+    the cell-node table, every node scattered with atomics): the headline box
+    given as a general mesh (same state and input, permuted to the canonical
+    numbering) and an unstructured cube-in-cube mesh of about the same size."""
+    import numpy as np
+    import torch
+    from scipy.spatial import cKDTree
+
+    import paper_2505_15535_amd as mfe
+    import synthetic
+
+    dev = torch.device("cuda", 0)
+    cfg = synthetic.get_config(name)
+    verts = cfg.vertices()
+    box = mfe.Operator(cfg.nx, cfg.ny, cfg.nz, cfg.degree, verts, cfg.mu, cfg.lam, device=0)
+    box_xyz = box.node_coordinates()
+    box.close()
+    meshes = [("box_as_hex", f"{cfg.description}, given as a general mesh (cells in box order)", verts,
+               synthetic.box_cells(cfg.nx, cfg.ny, cfg.nz), "box")]
+    v2, c2 = synthetic.cube_in_cube(25, jitter=0.1, rng=np.random.default_rng(3))
+    meshes.append(("cube_in_cube25_q2", "unit cube as a central cube and six shells, 7 x 25^3 = 109,375 "
+                   "jittered Q2 cells, 3^3 Gauss", v2, c2, "sine"))
+    out = {}
+    for key, desc, vv, cc, state in meshes:
+        op = mfe.Operator.from_hex(vv, cc, cfg.degree, cfg.mu, cfg.lam, device=0)
+        xyz = op.node_coordinates()
+        if state == "box":   # the headline state and input, in the canonical numbering
+            d, perm = cKDTree(box_xyz).query(xyz)
+            assert d.max() < 1e-12
+            dm = (3 * perm[:, None] + np.arange(3)).reshape(-1)
+            u_h, w_h = cfg.displacement()[dm], cfg.test_vector(0)[dm]
+        else:
+            u_h = synthetic.sine_field(xyz, 0.03, np.random.default_rng(5))
+            w_h = np.random.default_rng(6).standard_normal(op.n_dofs)
+        op.set_state(torch.from_numpy(np.ascontiguousarray(u_h)).to(dev))
+        w = torch.from_numpy(np.ascontiguousarray(w_h)).to(dev)
+        v = torch.empty_like(w)
+        rec = {"workload": desc, "n_dofs": op.n_dofs, "cells": op.n_cells}
+        for s in strategies:
+            op.build_cache(s)
+            step_ms, kern_ms = time_applies(op, w, v, s, "fp64", steps, warmup)
+            model = hex_model(s, cfg.degree, op.n_dofs, op.n_qpoints, len(vv), op.n_cells)
+            rec[s] = {"ms_per_step": round(step_ms, 5), "kernel_ms": round(kern_ms, 5),
+                      "gdofs": round(op.n_dofs / (step_ms * 1e-3) / 1e9, 4),
+                      "roofline": roofline(model, kern_ms, measured_traffic(key, s))}
+            print(f"[bench] general mesh {key} {s}: {rec[s]['gdofs']:.2f} GDoF/s, kernel {kern_ms * 1e3:.1f} us, "
+                  f"{rec[s]['roofline']['frac'] * 100:.1f}% of {model['bound']} roof", file=sys.stderr, flush=True)
+        out[key] = rec
+        op.close()
+    return out
+
+
 # --------------------------------------------------------------------------- Newton-CG
 NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=8, max_cg=2000, newton_atol=1e-8,
                    cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0)
@@ -329,8 +398,9 @@ def main(argv=None):
     ap.add_argument("--mixed", default="box24_q4,box12_q6",
                     help="workloads of the FP64-vs-FP32 apply comparison (the headline one is added)")
     ap.add_argument("--no-newton", action="store_true")
-    ap.add_argument("--legs", default="apply,mixed,split,newton,learned",
-                    help="subset of apply,mixed,split,newton,learned to run (profiling runs; the default runs all)")
+    ap.add_argument("--legs", default="apply,mixed,split,hex,newton,learned",
+                    help="subset of apply,mixed,split,hex,newton,learned to run (profiling runs; the default runs "
+                         "all)")
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (reference for HBM counters)")
@@ -419,6 +489,8 @@ def main(argv=None):
                              for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
         if "split" in legs:
             line["split"] = split_leg(cfg.name, args.steps, args.warmup)
+        if "hex" in legs:
+            line["hex"] = hex_leg(cfg.name, args.steps, args.warmup)
         if "newton" in legs and not args.no_newton:
             line["newton"] = newton_leg()
         if "learned" in legs:
@@ -453,6 +525,8 @@ def main(argv=None):
                          for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
     if "split" in legs:
         line["split"] = split_leg(cfg.name, args.steps, args.warmup)
+    if "hex" in legs:
+        line["hex"] = hex_leg(cfg.name, args.steps, args.warmup)
     if "newton" in legs and not args.no_newton:
         line["newton"] = newton_leg()
     if "learned" in legs:
