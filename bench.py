@@ -294,7 +294,8 @@ def hex_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
 
 # --------------------------------------------------------------------------- Newton-CG
 NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=8, max_cg=2000, newton_atol=1e-8,
-                   cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0)
+                   cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0,
+                   coarse_direct=1)
 
 
 def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:

@@ -291,6 +291,14 @@ typedef struct mfe_solve_opts {
     int mg_graph;         /* GMG: 1 = replay each V-cycle from a HIP graph
                              (captured on a private stream after every level
                              update; kernel nodes only), 0 = launch eagerly */
+    int coarse_direct;    /* GMG: 1 = solve the coarsest level exactly when it has
+                             at most 196 free dofs and 1024 dofs in all (its
+                             dense tangent, assembled from the second-order
+                             cache, is inverted on the device once per
+                             linearisation point; if it is not positive
+                             definite, or larger, the level is smoothed as
+                             with 0), 0 = Chebyshev smoothing with
+                             coarse_degree and coarse_range */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64

@@ -212,6 +212,15 @@ struct MGLevel {
     MGVec<float> v32;
     double* rnd = nullptr;     // fixed random start of the eigenvalue estimate
     double lmax = 0.0;         // estimate of the largest eigenvalue of D^-1 K
+    // coarsest level solved directly: the inverse of its tangent on the nf
+    // free dofs (nf x nf, followed by the n x n assembled tangent), an FP32
+    // copy, and the maps dof -> free row (-1: constrained), row -> dof
+    double* dense = nullptr;
+    float* dense32 = nullptr;
+    int* dense_pos = nullptr;
+    int* dense_free = nullptr;
+    int dense_nf = 0;
+    bool dense_ok = false;
     // per axis, between this level and the next coarser one: prolongation
     // (fine x coarse), restriction (its transpose) and interpolation of the
     // state to the coarse nodes (coarse x fine)
@@ -279,9 +288,11 @@ struct mfe_ctx {
     const double* mg_graph_r = nullptr;
     double* mg_graph_z = nullptr;
     int mg_graph_prec = -1;
+    mfe_solve_opts mg_graph_opts = {};
     // what the level data were last set up for
     uint64_t mg_ready_version = 0;
     int mg_ready_strategy = -1, mg_ready_prec = -1;
+    mfe_solve_opts mg_ready_opts = {};
     // learned smoother correction: network parameters, node invariants of the
     // state, per-patch buffers of the preconditioner
     float* d_net = nullptr;
@@ -337,6 +348,10 @@ void mg_free(mfe_ctx* c) {
     for (auto& L : c->mg) {
         dfree(L.vec);
         dfree(L.vec32);
+        dfree(L.dense);
+        dfree(L.dense32);
+        dfree(L.dense_pos);
+        dfree(L.dense_free);
         for (int a = 0; a < 3; ++a) {
             free_csr(L.P[a]);
             free_csr(L.R[a]);
@@ -991,6 +1006,7 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
         if (o->mg_precision != MFE_FP64 && o->mg_precision != MFE_SF_FP32)
             return fail(c, MFE_EINVAL, "mg_precision must be MFE_FP64 or MFE_SF_FP32");
         if (o->mg_graph != 0 && o->mg_graph != 1) return fail(c, MFE_EINVAL, "mg_graph must be 0 or 1");
+        if (o->coarse_direct != 0 && o->coarse_direct != 1) return fail(c, MFE_EINVAL, "coarse_direct must be 0 or 1");
     }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
@@ -1378,6 +1394,53 @@ int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
 // Per linearisation point: interpolate the state to every coarser level,
 // build the level caches (in the V-cycle's precision), the inverse diagonals
 // and an estimate of the largest eigenvalue of D^-1 K.
+// Inverse of the coarsest level's tangent on its free dofs, from its
+// second-order cache, which must be current.  ok = false when there are
+// more than kDenseMax free dofs or the tangent is not positive definite
+// (then the level is smoothed instead).
+int dense_setup(mfe_ctx* c, MGLevel& L, bool fp32, hipStream_t s, bool& ok) {
+    ok = false;
+    mfe_ctx* lc = L.ctx;
+    const int n = (int)lc->n_dofs;
+    if (!L.dense) {  // the constraints of a level are fixed for the life of the hierarchy
+        std::vector<int> pos(n, 0), free_idx;
+        for (int64_t d : lc->h_cidx) pos[d] = -1;
+        for (int d = 0; d < n; ++d)
+            if (pos[d] == 0) {
+                pos[d] = (int)free_idx.size();
+                free_idx.push_back(d);
+            }
+        L.dense_nf = (int)free_idx.size();
+        if (L.dense_nf == 0 || L.dense_nf > mfe::kDenseMax) return MFE_OK;
+        const size_t nf2 = (size_t)L.dense_nf * L.dense_nf;
+        MFE_HIP(c, hipMalloc(&L.dense, (nf2 + (size_t)n * n) * sizeof(double)));
+        MFE_HIP(c, hipMalloc(&L.dense_pos, n * sizeof(int)));
+        MFE_HIP(c, hipMalloc(&L.dense_free, L.dense_nf * sizeof(int)));
+        MFE_HIP(c, hipMemcpy(L.dense_pos, pos.data(), n * sizeof(int), hipMemcpyHostToDevice));
+        MFE_HIP(c, hipMemcpy(L.dense_free, free_idx.data(), L.dense_nf * sizeof(int), hipMemcpyHostToDevice));
+    }
+    const int nf = L.dense_nf;
+    const size_t nf2 = (size_t)nf * nf;
+    double* A = L.dense + nf2;
+    MFE_HIP(c, mfe::launch_fill(A, (int64_t)n * n, 0.0, s));
+    KParams p = base_params(lc);
+    p.cache = lc->d_cache[1];
+    MFE_HIP(c, mfe::launch_dense_tangent(lc->tab, p, A, n, s));
+    MFE_HIP(c, mfe::launch_sweep_inverse(A, n, L.dense_free, nf, L.dense, c->d_bad, s));
+    int bad = 1;
+    MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipStreamSynchronize(s));
+    ok = bad == 0;
+    if (ok && fp32) {
+        if (!L.dense32) MFE_HIP(c, hipMalloc(&L.dense32, nf2 * sizeof(float)));
+        MFE_HIP(c, mfe::launch_convert(L.dense, L.dense32, (int64_t)nf2, s));
+    }
+    return MFE_OK;
+}
+
+const double* dense_of(const MGLevel& L, double*) { return L.dense; }
+const float* dense_of(const MGLevel& L, float*) { return L.dense32; }
+
 int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
     const bool cached = o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD;
     const bool fp32 = o->mg_precision == MFE_SF_FP32;
@@ -1415,10 +1478,21 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
         MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
         if (bad) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
-        double lam = 0.0;
-        rc = lanczos_lmax(c, L, s, lam);
-        if (rc != MFE_OK) return rc;
-        L.lmax = lam;
+        L.dense_ok = false;
+        const int64_t n_free = lc->n_dofs - lc->n_con;
+        if (o->coarse_direct && l + 1 == c->mg.size() && lc->n_dofs <= 1024 && n_free > 0 &&
+            n_free <= mfe::kDenseMax) {
+            rc = dense_setup(c, L, fp32, s, L.dense_ok);
+            if (rc != MFE_OK) return rc;
+        }
+        if (L.dense_ok) {
+            L.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
+        } else {
+            double lam = 0.0;
+            rc = lanczos_lmax(c, L, s, lam);
+            if (rc != MFE_OK) return rc;
+            L.lmax = lam;
+        }
         // the V-cycle works on the free dofs: the smoother never moves a
         // constrained entry, and its operator-output buffer starts cleared
         if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.v64.dinv, s));
@@ -1432,6 +1506,7 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
     c->mg_ready_version = c->state_version;
     c->mg_ready_strategy = o->strategy;
     c->mg_ready_prec = o->mg_precision;
+    c->mg_ready_opts = *o;
     return MFE_OK;
 }
 
@@ -1472,7 +1547,14 @@ template <typename T>
 int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipStream_t s) {
     MGLevel& L = c->mg[l];
     MGVec<T>& V = L.vecs(static_cast<T*>(nullptr));
-    if (l + 1 == c->mg.size()) return chebyshev(c, o, L, b, x, o->coarse_degree, o->coarse_range, true, s);
+    if (l + 1 == c->mg.size()) {
+        if (L.dense_ok) {
+            MFE_HIP(c, mfe::launch_dense_matvec(dense_of(L, static_cast<T*>(nullptr)), L.dense_pos, L.dense_free,
+                                                L.dense_nf, b, x, (int)L.ctx->n_dofs, s));
+            return MFE_OK;
+        }
+        return chebyshev(c, o, L, b, x, o->coarse_degree, o->coarse_range, true, s);
+    }
     int rc = chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, true, s);
     if (rc != MFE_OK) return rc;
     // K x into V.r; the restriction forms the free residual b - K x on the fly
@@ -1518,7 +1600,12 @@ int gmg_body(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hi
 // kernel by kernel.  The graph holds kernel nodes only.
 int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s) {
     if (!o->mg_graph) return gmg_body(c, o, r, z, s);
-    if (!c->mg_graph_valid || c->mg_graph_r != r || c->mg_graph_z != z || c->mg_graph_prec != o->mg_precision) {
+    const mfe_solve_opts& go = c->mg_graph_opts;
+    const bool same = go.cheb_degree == o->cheb_degree && go.cheb_range == o->cheb_range &&
+                      go.coarse_degree == o->coarse_degree && go.coarse_range == o->coarse_range &&
+                      go.coarse_direct == o->coarse_direct && go.strategy == o->strategy;
+    if (!c->mg_graph_valid || !same || c->mg_graph_r != r || c->mg_graph_z != z ||
+        c->mg_graph_prec != o->mg_precision) {
         if (c->mg_exec) {
             (void)hipGraphExecDestroy(c->mg_exec);
             c->mg_exec = nullptr;
@@ -1543,6 +1630,7 @@ int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, h
         c->mg_graph_r = r;
         c->mg_graph_z = z;
         c->mg_graph_prec = o->mg_precision;
+        c->mg_graph_opts = *o;
     }
     MFE_HIP(c, hipGraphLaunch(c->mg_exec, s));
     return MFE_OK;
@@ -1927,8 +2015,11 @@ int mfe_gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* 
     if (rc != MFE_OK) return rc;
     if (!r || !z) return fail(c, MFE_EINVAL, "null vector");
     if (overlaps(r, z, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "r and z overlap");
+    const mfe_solve_opts& m = c->mg_ready_opts;
     if (c->mg.empty() || c->mg_request != o2.mg_levels || c->mg_ready_version != c->state_version ||
-        c->mg_ready_strategy != o2.strategy || c->mg_ready_prec != o2.mg_precision)
+        c->mg_ready_strategy != o2.strategy || c->mg_ready_prec != o2.mg_precision ||
+        m.cheb_degree != o2.cheb_degree || m.cheb_range != o2.cheb_range || m.coarse_degree != o2.coarse_degree ||
+        m.coarse_range != o2.coarse_range || m.coarse_direct != o2.coarse_direct)
         return fail(c, MFE_ESTATE, "multigrid level data not set up for this state and these options");
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -770,6 +770,92 @@ __global__ __launch_bounds__((Geo<N, HX>::NT)) void diag_kernel(const KParams p,
 }
 
 // ---------------------------------------------------------------------------
+// Dense tangent of a small mesh (the coarsest multigrid level) from the
+// second-order cache: with g^a = (dN_a/dxi) M at a point,
+//   K_(a,i),(b,j) = sum_q [ c1 g^a_i g^b_j + c2/2 (delta_ij g^a.g^b + g^a_j g^b_i)
+//                           + delta_ij g^a tau g^b ],
+// the T2 point-wise product applied to w = N_b e_j and tested with N_a e_i.
+// One workgroup per cell, one thread per pair of local nodes; entries are
+// added into A (n x n, row-major, dof = 3 node + component) with atomics.
+// ---------------------------------------------------------------------------
+template <int N, bool HX>
+__global__ __launch_bounds__(256) void dense_kernel(const KParams p, const DiagTables T, double* __restrict__ A,
+                                                    int64_t n) {
+    using G = Geo<N, HX>;
+    constexpr int N3 = G::N3, P = G::P;
+    __shared__ double sS[N * N], sSd[N * N];
+    const int tid = threadIdx.x;
+    if (tid < N * N) {
+        sS[tid] = T.S[tid / N][tid % N];
+        sSd[tid] = T.Sd[tid / N][tid % N];
+    }
+    __syncthreads();
+    const int cell = blockIdx.x;
+    int ex = 0, ey = 0, ez = 0, brick, lc;
+    if constexpr (HX) {
+        brick = cell / G::CPB;
+        lc = cell - brick * G::CPB;
+    } else {
+        ex = cell % p.nx;
+        ey = (cell / p.nx) % p.ny;
+        ez = cell / (p.nx * p.ny);
+        const int bx = ex / G::BX, by = ey / G::BY, bz = ez / G::BZ;
+        brick = bx + p.nbx * (by + p.nby * bz);
+        lc = (ex - bx * G::BX) + G::BX * ((ey - by * G::BY) + G::BY * (ez - bz * G::BZ));
+    }
+    const double* cache = p.cache + (int64_t)brick * kT2Fields * G::NQ + lc * N3;
+    for (int pr = tid; pr < N3 * N3; pr += blockDim.x) {
+        const int a = pr / N3, b = pr - a * N3;
+        const int ai = a % N, aj = (a / N) % N, ak = a / G::N2;
+        const int bi = b % N, bj = (b / N) % N, bk = b / G::N2;
+        double K[3][3] = {};
+        for (int q = 0; q < N3; ++q) {
+            const int qx = q % N, qy = (q / N) % N, qz = q / G::N2;
+            const double da[3] = {sSd[qx * N + ai] * sS[qy * N + aj] * sS[qz * N + ak],
+                                  sS[qx * N + ai] * sSd[qy * N + aj] * sS[qz * N + ak],
+                                  sS[qx * N + ai] * sS[qy * N + aj] * sSd[qz * N + ak]};
+            const double db[3] = {sSd[qx * N + bi] * sS[qy * N + bj] * sS[qz * N + bk],
+                                  sS[qx * N + bi] * sSd[qy * N + bj] * sS[qz * N + bk],
+                                  sS[qx * N + bi] * sS[qy * N + bj] * sSd[qz * N + bk]};
+            double M[9], t[6];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) M[f] = cache[f * G::NQ + q];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) t[f] = cache[(9 + f) * G::NQ + q];
+            const double c1 = cache[15 * G::NQ + q], c2 = cache[16 * G::NQ + q];
+            double ga[3], gb[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                ga[m] = fma(da[0], M[m], fma(da[1], M[3 + m], da[2] * M[6 + m]));
+                gb[m] = fma(db[0], M[m], fma(db[1], M[3 + m], db[2] * M[6 + m]));
+            }
+            const double gab = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+            const double gtg = ga[0] * (t[0] * gb[0] + t[5] * gb[1] + t[4] * gb[2]) +
+                               ga[1] * (t[5] * gb[0] + t[1] * gb[1] + t[3] * gb[2]) +
+                               ga[2] * (t[4] * gb[0] + t[3] * gb[1] + t[2] * gb[2]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) K[i][j] += c1 * ga[i] * gb[j] + 0.5 * c2 * ga[j] * gb[i];
+                K[i][i] += 0.5 * c2 * gab + gtg;
+            }
+        }
+        int64_t na, nb;
+        if constexpr (HX) {
+            na = p.conn[(int64_t)cell * N3 + a];
+            nb = p.conn[(int64_t)cell * N3 + b];
+        } else {
+            na = (P * ex + ai) + (int64_t)p.Nx * ((P * ey + aj) + (int64_t)p.Ny * (P * ez + ak));
+            nb = (P * ex + bi) + (int64_t)p.Nx * ((P * ey + bj) + (int64_t)p.Ny * (P * ez + bk));
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) unsafeAtomicAdd(A + (3 * na + i) * n + 3 * nb + j, K[i][j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launch
 // ---------------------------------------------------------------------------
 template <int N>
@@ -896,6 +982,20 @@ static hipError_t launch_diag_n(const Tables1D& t, const KParams& p, double* dia
         }
     const int nb = p.nbx * p.nby * p.nbz;
     hipLaunchKernelGGL((diag_kernel<N, HX>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, diag);
+    return hipGetLastError();
+}
+
+template <int N, bool HX>
+static hipError_t launch_dense_n(const Tables1D& t, const KParams& p, double* A, int64_t n, hipStream_t stream) {
+    DiagTables T;
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+            T.S[a][b] = t.S[a][b];
+            double s = 0.0;  // derivative of the nodal basis at the Gauss points: D S
+            for (int l = 0; l < t.n; ++l) s += t.D[a][l] * t.S[l][b];
+            T.Sd[a][b] = (a < t.n && b < t.n) ? s : 0.0;
+        }
+    hipLaunchKernelGGL((dense_kernel<N, HX>), dim3(p.ne), dim3(256), 0, stream, p, T, A, n);
     return hipGetLastError();
 }
 

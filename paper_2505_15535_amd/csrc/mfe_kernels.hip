@@ -45,6 +45,20 @@ hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hi
     }
 }
 
+hipError_t launch_dense_tangent(const Tables1D& t, const KParams& p, double* A, int64_t n, hipStream_t stream) {
+    if (p.ne <= 0) return hipSuccess;
+    if (p.conn) return hipErrorInvalidValue;  // structured boxes only
+    switch (t.n) {
+        case 2: return launch_dense_n<2, false>(t, p, A, n, stream);
+        case 3: return launch_dense_n<3, false>(t, p, A, n, stream);
+        case 4: return launch_dense_n<4, false>(t, p, A, n, stream);
+        case 5: return launch_dense_n<5, false>(t, p, A, n, stream);
+        case 6: return launch_dense_n<6, false>(t, p, A, n, stream);
+        case 7: return launch_dense_n<7, false>(t, p, A, n, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32) {
     if (p.ne <= 0) return hipSuccess;
     if (p.conn) return launch_cell_kernel_hex(mode, t, p, stream, fp32);

@@ -97,6 +97,22 @@ struct DiagTables {
 hipError_t launch_diagonal(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
 hipError_t launch_diagonal_hex(const Tables1D& t, const KParams& p, double* diag, hipStream_t stream);
 
+// A += dense tangent of a structured box (n = its dof count, A row-major
+// n x n) from the second-order cache in p.cache.
+hipError_t launch_dense_tangent(const Tables1D& t, const KParams& p, double* A, int64_t n, hipStream_t stream);
+// Ainv (nf x nf) = inverse of the block of A (n x n, row-major) on the dofs
+// free_idx[0..nf), nf <= kDenseMax, for a symmetric positive definite block;
+// *fail = 1 (Ainv undefined) when a pivot is not positive and finite.  One
+// workgroup, the block in LDS.
+constexpr int kDenseMax = 196;
+hipError_t launch_sweep_inverse(const double* A, int n, const int* free_idx, int nf, double* Ainv, int* fail,
+                                hipStream_t s);
+// x = Ainv b on the free dofs (pos[dof] = its row of Ainv, or -1 for a
+// constrained dof, where x = 0)
+hipError_t launch_dense_matvec(const double* Ainv, const int* pos, const int* free_idx, int nf, const double* b,
+                               double* x, int n, hipStream_t s);
+hipError_t launch_dense_matvec(const float* Ainv, const int* pos, const int* free_idx, int nf, const float* b,
+                               float* x, int n, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t stream);
 hipError_t launch_fill(float* x, int64_t n, float value, hipStream_t stream);
 

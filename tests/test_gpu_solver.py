@@ -136,11 +136,13 @@ def test_gmg_fp32_vcycle_defect_correction(torch_dev):
         assert it <= 1.25 * res["fp64", "t2"][1] + 2, k
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_gmg_preconditioner_graph_and_symmetry(torch_dev, prec, tol):
+@pytest.mark.parametrize("prec,tol,direct", [("fp64", 1e-12, 1), ("fp32", 1e-5, 1), ("fp64", 1e-12, 0),
+                                             ("fp32", 1e-5, 0)])
+def test_gmg_preconditioner_graph_and_symmetry(torch_dev, prec, tol, direct):
     """One V-cycle replayed from the HIP graph equals the eagerly launched one
     on every replay (with other GPU work in between), B is symmetric and
-    positive, and it is the identity on the constrained dofs."""
+    positive, and it is the identity on the constrained dofs; with the
+    coarsest level (4x1x1, 243 dofs) solved directly or smoothed."""
     import paper_2505_15535_amd as mfe
     torch, dev = torch_dev
     nx, ny, nz, L = 16, 4, 4, (4.0, 1.0, 1.0)
@@ -153,7 +155,7 @@ def test_gmg_preconditioner_graph_and_symmetry(torch_dev, prec, tol):
     op.set_state(u)
     op.build_cache("t2")
     R = [_to(torch_dev, r) for r in synthetic.random_vectors(op.n_dofs, 2, synthetic.rng_for(92, 2))]
-    opts = dict(strategy="t2", mg_precision=prec)
+    opts = dict(strategy="t2", mg_precision=prec, coarse_direct=direct)
     with pytest.raises(mfe.MfeError) as e:
         op.gmg_apply(R[0], **opts)          # level data not set up yet
     assert e.value.code == mfe.MFE_ESTATE
@@ -175,8 +177,11 @@ def test_gmg_preconditioner_graph_and_symmetry(torch_dev, prec, tol):
     # the FP32 V-cycle really runs in FP32: it differs from the FP64 one at the
     # level of FP32 rounding, not more
     other = "fp64" if prec == "fp32" else "fp32"
-    op.gmg_setup(strategy="t2", mg_precision=other)
-    zo = op.gmg_apply(R[0], strategy="t2", mg_precision=other)
+    op.gmg_setup(strategy="t2", mg_precision=other, coarse_direct=direct)
+    with pytest.raises(mfe.MfeError) as e:
+        op.gmg_apply(R[0], strategy="t2", mg_precision=other, coarse_direct=1 - direct)   # other options
+    assert e.value.code == mfe.MFE_ESTATE
+    zo = op.gmg_apply(R[0], strategy="t2", mg_precision=other, coarse_direct=direct)
     d = float(torch.linalg.norm(zo - z0) / torch.linalg.norm(z0))
     assert 1e-10 < d < 1e-4, d
     op.set_state(0.5 * u)
@@ -286,3 +291,39 @@ def test_cg_reports_breakdown_on_indefinite_tangent(torch_dev):
     x, it, rel, status = op.cg_solve(_to(torch_dev, b), strategy="t2", preconditioner="none", max_cg=30000,
                                      cg_rtol=1e-12)
     assert status == "MFE_ENOTCONV"
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_gmg_single_level_is_a_direct_solve(torch_dev, prec, tol):
+    """With one level (135 dofs, 108 free) and coarse_direct the preconditioner is the
+    exact inverse of the tangent on the free dofs (identity on the
+    constrained ones): against the oracle's sparse direct solve.  The FP32
+    V-cycle applies the FP64 inverse rounded to FP32 (bound 1e-4: the
+    rounding of the entries times the conditioning of the product).  CG
+    with it converges in one iteration; without coarse_direct the level is
+    only smoothed."""
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz = 2, 1, 1
+    verts = synthetic.box_vertices(nx, ny, nz, (1.0, 0.8, 0.7), 0.1, synthetic.rng_for(95, 0))
+    mesh = BoxMesh(nx, ny, nz, 2, verts)
+    u = synthetic.sine_displacement(nx, ny, nz, 2, 0.002, synthetic.rng_for(95, 1))   # K SPD, cond 8e3
+    left = np.where(mesh.node_positions()[:, 0] < 1e-12)[0]
+    cdofs = (3 * left[:, None] + np.arange(3)).ravel()
+    P = Problem(mesh, 1.0, 10.0, constrained_dofs=cdofs)
+    K = P.assemble_tangent(u).tocsc()
+    r = synthetic.random_vectors(mesh.n_dofs, 1, synthetic.rng_for(95, 2))[0]
+    ref = spla.spsolve(K, r)
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, 10.0, device=0)
+    op.set_constraints(cdofs)
+    op.set_state(_to(torch_dev, u))
+    opts = dict(strategy="t2", mg_levels=1, mg_precision=prec, coarse_direct=1)
+    op.gmg_setup(**opts)
+    z = op.gmg_apply(_to(torch_dev, r), **opts).cpu().numpy()
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) <= tol
+    x, it, rel, status = op.cg_solve(_to(torch_dev, r), preconditioner="gmg", cg_rtol=1e-4, max_cg=50, **opts)
+    assert status == "MFE_OK" and it <= 2, (it, rel)
+    smooth = dict(opts, coarse_direct=0)
+    op.gmg_setup(**smooth)
+    z2 = op.gmg_apply(_to(torch_dev, r), **smooth).cpu().numpy()
+    assert np.linalg.norm(z2 - ref) / np.linalg.norm(ref) > 1e-3
