@@ -236,10 +236,16 @@ struct mfe_ctx {
     bool has_mesh = false;
     // general hexahedral mesh (mfe_mesh_hex): nx = ny = nz = 0, cells gathered
     // through the cell-node table d_conn, geometry from d_ev
+    // Cells are processed in an internal order (Morton order of their
+    // centroids, h_perm[internal] = caller's index) in groups of consecutive
+    // cells, each group with its list of distinct nodes (d_gnodes, padded
+    // with -1) and every cell node's position in that list (d_lidx).
     bool hex = false;
     int* d_conn = nullptr;
     int* d_ev = nullptr;
-    std::vector<int32_t> h_ev, h_conn;
+    int* d_gnodes = nullptr;
+    unsigned short* d_lidx = nullptr;
+    std::vector<int32_t> h_ev, h_conn, h_perm;
     int nx = 0, ny = 0, nz = 0, degree = 0;
     int Nx = 0, Ny = 0, Nz = 0;
     int64_t n_nodes = 0, n_dofs = 0, ne = 0, nq = 0;
@@ -377,9 +383,12 @@ void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_verts);
     dfree(c->d_conn);
     dfree(c->d_ev);
+    dfree(c->d_gnodes);
+    dfree(c->d_lidx);
     c->hex = false;
     c->h_ev.clear();
     c->h_conn.clear();
+    c->h_perm.clear();
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
     dfree(c->d_cidx);
@@ -413,6 +422,8 @@ KParams base_params(const mfe_ctx* c) {
     p.cell_mat = c->d_cellmat;
     p.conn = c->d_conn;
     p.ev = c->d_ev;
+    p.gnodes = c->d_gnodes;
+    p.lidx = c->d_lidx;
     p.mu = c->mu;
     p.lam = c->lam;
     p.flag = c->d_flag;
@@ -617,6 +628,29 @@ int mfe_mesh_hex(mfe_ctx* c, int64_t nv, const double* vxyz, int64_t ne, const i
         const int rc = check_cell_geometry(c, X, t, e);
         if (rc != MFE_OK) return rc;
     }
+    // internal cell order and the per-group node lists
+    std::vector<int32_t> perm;
+    mfe::morton_order(nv, vxyz, ne, ev, perm);
+    int cells, ppg;
+    mfe::hex_group_shape(n, &cells, &ppg);
+    const int64_t n_groups = (ne + cells - 1) / cells;
+    const int maxu = cells * n3;
+    std::vector<int32_t> ev_i((size_t)ne * 8), conn_i((size_t)ne * n3), gnodes((size_t)n_groups * maxu, -1);
+    std::vector<unsigned short> lidx((size_t)ne * n3);
+    for (int64_t e = 0; e < ne; ++e) {
+        std::copy(ev + 8 * (int64_t)perm[e], ev + 8 * (int64_t)perm[e] + 8, ev_i.begin() + 8 * e);
+        std::copy(conn.begin() + n3 * (int64_t)perm[e], conn.begin() + n3 * (int64_t)perm[e] + n3,
+                  conn_i.begin() + n3 * e);
+    }
+    for (int64_t gi = 0; gi < n_groups; ++gi) {
+        const int64_t e0 = gi * cells, e1 = std::min<int64_t>(ne, e0 + cells);
+        std::vector<int32_t> u(conn_i.begin() + e0 * n3, conn_i.begin() + e1 * n3);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        std::copy(u.begin(), u.end(), gnodes.begin() + gi * maxu);
+        for (int64_t t = e0 * n3; t < e1 * n3; ++t)
+            lidx[t] = (unsigned short)(std::lower_bound(u.begin(), u.end(), conn_i[t]) - u.begin());
+    }
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, MFE_EHIP, "hipSetDevice failed");
     MFE_HIP(c, hipDeviceSynchronize());
@@ -624,13 +658,18 @@ int mfe_mesh_hex(mfe_ctx* c, int64_t nv, const double* vxyz, int64_t ne, const i
     MFE_HIP(c, hipMalloc(&c->d_verts, nv * 3 * sizeof(double)));
     MFE_HIP(c, hipMemcpy(c->d_verts, vxyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice));
     MFE_HIP(c, hipMalloc(&c->d_ev, ne * 8 * sizeof(int32_t)));
-    MFE_HIP(c, hipMemcpy(c->d_ev, ev, ne * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMemcpy(c->d_ev, ev_i.data(), ne * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
     MFE_HIP(c, hipMalloc(&c->d_conn, ne * n3 * sizeof(int32_t)));
-    MFE_HIP(c, hipMemcpy(c->d_conn, conn.data(), ne * n3 * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMemcpy(c->d_conn, conn_i.data(), ne * n3 * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_gnodes, gnodes.size() * sizeof(int32_t)));
+    MFE_HIP(c, hipMemcpy(c->d_gnodes, gnodes.data(), gnodes.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MFE_HIP(c, hipMalloc(&c->d_lidx, lidx.size() * sizeof(unsigned short)));
+    MFE_HIP(c, hipMemcpy(c->d_lidx, lidx.data(), lidx.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
     MFE_HIP(c, hipMalloc(&c->d_u, 3 * n_nodes * sizeof(double)));
     c->h_verts.assign(vxyz, vxyz + nv * 3);
-    c->h_ev.assign(ev, ev + ne * 8);
-    c->h_conn.swap(conn);
+    c->h_ev.swap(ev_i);
+    c->h_conn.swap(conn_i);
+    c->h_perm.swap(perm);
     c->h_cellmat.clear();
     c->h_cidx.clear();
     c->hex = true;
@@ -641,9 +680,7 @@ int mfe_mesh_hex(mfe_ctx* c, int64_t nv, const double* vxyz, int64_t ne, const i
     c->n_dofs = 3 * n_nodes;
     c->ne = ne;
     c->nq = ne * n3;
-    int cells, ppg;
-    mfe::hex_group_shape(n, &cells, &ppg);
-    c->nbx = (int)((ne + cells - 1) / cells);
+    c->nbx = (int)n_groups;
     c->nby = c->nbz = 1;
     c->nq_stride = (int64_t)c->nbx * ppg;
     c->tab = t;
@@ -691,8 +728,18 @@ int mfe_set_material(mfe_ctx* c, double mu, double lam, const double* per_cell) 
     c->h_cellmat.clear();
     if (per_cell) {
         c->h_cellmat.assign(per_cell, per_cell + 2 * c->ne);
+        std::vector<double> internal;
+        const double* src = per_cell;
+        if (c->hex) {  // the kernels read cells in their internal order
+            internal.resize(2 * c->ne);
+            for (int64_t e = 0; e < c->ne; ++e) {
+                internal[2 * e] = per_cell[2 * (int64_t)c->h_perm[e]];
+                internal[2 * e + 1] = per_cell[2 * (int64_t)c->h_perm[e] + 1];
+            }
+            src = internal.data();
+        }
         MFE_HIP(c, hipMalloc(&c->d_cellmat, c->ne * 2 * sizeof(double)));
-        MFE_HIP(c, hipMemcpy(c->d_cellmat, per_cell, c->ne * 2 * sizeof(double), hipMemcpyHostToDevice));
+        MFE_HIP(c, hipMemcpy(c->d_cellmat, src, c->ne * 2 * sizeof(double), hipMemcpyHostToDevice));
     }
     c->mu = mu;
     c->lam = lam;

@@ -55,8 +55,8 @@ template <> struct BrickDims<7> { static constexpr int BX = 1, BY = 1, BZ = 1; }
 // HX = false: a brick of neighbouring cells of a structured box, whose cells
 // share their face nodes in the LDS node array.  HX = true: a group of the
 // same number of consecutive cells of a general hexahedral mesh (cells listed
-// in x, BY = BZ = 1), each with its own n^3 nodes in the LDS node array and
-// its global node ids read from the cell-node table.
+// in x, BY = BZ = 1); the LDS node array holds the group's distinct nodes
+// (at most cells x n^3 slots) and a table of slots addresses each cell node.
 template <int N, bool HX = false>
 struct Geo {
     static constexpr int P = N - 1, N2 = N * N, N3 = N2 * N;
@@ -159,17 +159,16 @@ __device__ __forceinline__ BrickMap<N, HX> brick_map(const KParams& p, const Bri
     m.exists = 0u;
     m.face = 0u;
     if constexpr (HX) {
-        // entry e = (cell lc, local node a, component c); every node may be
-        // shared with cells outside the group
+        // entry e = (slot e / 3 of the group's node list, component e % 3);
+        // every node may be shared with cells outside the group
+        constexpr int MAXU = G::CPB * G::N3;
 #pragma unroll
         for (int k = 0; k < G::GPT; ++k) {
             const int e = threadIdx.x + k * G::NT;
-            const int lc = e / (3 * G::N3);
-            const int r = e - lc * (3 * G::N3);
-            const int a = r / 3;
-            const bool ex = e < G::BRICK && lc < bp.ncx;
-            m.dof[k] = ex ? 3 * p.conn[(int64_t)(bp.ex0 + lc) * G::N3 + a] + (r - 3 * a) : 0;
-            if (ex) m.exists |= 1u << k;
+            const int u = e / 3;
+            const int node = e < G::BRICK ? p.gnodes[(int64_t)bp.brick * MAXU + u] : -1;
+            m.dof[k] = node >= 0 ? 3 * node + (e - 3 * u) : 0;
+            if (node >= 0) m.exists |= 1u << k;
             m.face |= 1u << k;
         }
         return m;
@@ -206,13 +205,14 @@ __device__ __forceinline__ void brick_store(R* sBrick, const R (&r)[Geo<N, HX>::
     }
 }
 
-// Offset in the brick node array of node (0, j, k) of line L's cell, component
-// L.c (nodes along x follow with stride 3).
+// Offset in the brick node array of node (i, j, k) of line L's cell,
+// component L.c: along x-rows of the brick, or through the group's slot table
+// sL (general meshes).
 template <int N, bool HX>
-__device__ __forceinline__ int brick_row(const Line& L, int j, int k) {
+__device__ __forceinline__ int brick_node(const Line& L, int i, int j, int k, const unsigned short* sL) {
     using G = Geo<N, HX>;
-    if constexpr (HX) return ((L.lc * N + k) * N + j) * G::ROW + L.c;
-    else return ((G::P * L.lz + k) * G::GY + (G::P * L.ly + j)) * G::ROW + 3 * G::P * L.lx + L.c;
+    if constexpr (HX) return 3 * sL[L.lc * G::N3 + i + N * (j + N * k)] + L.c;
+    else return ((G::P * L.lz + k) * G::GY + (G::P * L.ly + j)) * G::ROW + 3 * (G::P * L.lx + i) + L.c;
 }
 
 // LDS layout.  sG holds 9 doubles per quadrature point, addressed as
@@ -234,7 +234,7 @@ __device__ __forceinline__ int gofs(int lc, int idx, int c) {
 // ---------------------------------------------------------------------------
 template <int N, bool HX, typename R>
 __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<N, R>& T, R* sG, R* sV,
-                                               R* sBrick, bool clear_brick) {
+                                               R* sBrick, bool clear_brick, const unsigned short* sL) {
     using G = Geo<N, HX>;
     constexpr int N2 = G::N2;
     // x: interpolate every cell's node x-rows -> slot 0 at (qx, j, k)
@@ -243,10 +243,9 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
         const Line L = line_of<N, HX>(threadIdx.x + it * G::NT, bp);
         if (!L.valid) continue;
         const int j = L.a, k = L.b;
-        const R* row = sBrick + brick_row<N, HX>(L, j, k);
         R x[N], y[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = row[3 * i];
+        for (int i = 0; i < N; ++i) x[i] = sBrick[brick_node<N, HX>(L, i, j, k, sL)];
         apply_eo<N, false>(T.S, x, y);
         R* out = sG + gofs<N>(L.lc, N * (j + N * k), L.c);
 #pragma unroll
@@ -325,7 +324,8 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
 // ---------------------------------------------------------------------------
 template <int N, bool HX, typename R>
 __device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const BrickPos& bp, const BrickMap<N, HX>& bm,
-                                                const Tables<N, R>& T, R* sG, R* sV, R* sBrick) {
+                                                const Tables<N, R>& T, R* sG, R* sV, R* sBrick,
+                                                const unsigned short* sL) {
     using G = Geo<N, HX>;
     constexpr int N2 = G::N2;
     // transposed x- and y-derivatives, in place in slots 0 and 1
@@ -396,9 +396,8 @@ __device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const Brick
 #pragma unroll
         for (int qx = 0; qx < N; ++qx) x[qx] = sG[base + 9 * qx];
         apply_eo<N, false>(T.St, x, y);
-        R* row = sBrick + brick_row<N, HX>(L, j, k);
 #pragma unroll
-        for (int i = 0; i < N; ++i) atomicAdd(row + 3 * i, y[i]);
+        for (int i = 0; i < N; ++i) atomicAdd(sBrick + brick_node<N, HX>(L, i, j, k, sL), y[i]);
     }
     __syncthreads();
 #pragma unroll
@@ -495,10 +494,14 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
     __shared__ LT sV[G::NQ * 3];
     __shared__ LT sBrick[G::BRICK];
     __shared__ double sEdge[G::CPB * 36];
+    __shared__ unsigned short sL[HX ? G::CPB * N3 : 1];
 
     const BrickPos bp = brick_pos<N, HX>(p);
     const BrickMap<N, HX> bm = brick_map<N, HX>(p, bp);
     const int tid = threadIdx.x;
+    if constexpr (HX) {  // slot table of the group's cell nodes (read after the first barrier)
+        for (int t = tid; t < bp.ncx * N3; t += G::NT) sL[t] = p.lidx[(int64_t)bp.ex0 * N3 + t];
+    }
     // the quadrature point of this thread
     const int lc = tid / N3;
     const int q = tid - lc * N3;
@@ -589,7 +592,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         brick_store<N, HX>(reinterpret_cast<double*>(sBrick), ub);
         __syncthreads();
         forward_sweeps<N, HX>(bp, T, reinterpret_cast<double*>(sG), reinterpret_cast<double*>(sV),
-                          reinterpret_cast<double*>(sBrick), !MI::fwd_w);
+                              reinterpret_cast<double*>(sBrick), !MI::fwd_w, sL);
         if (active) {
             load_slots<N>(reinterpret_cast<const double*>(sG), tid, du);
             if constexpr (MODE == MODE_APPLY_OTF_GEOM) {
@@ -669,7 +672,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         // sBrick was last read before the forward sweeps' first barrier
         brick_store<N, HX>(bW, wb);
         __syncthreads();
-        forward_sweeps<N, HX>(bp, TR, gW, vW, bW, true);
+        forward_sweeps<N, HX>(bp, TR, gW, vW, bW, true, sL);
         if (active) {
             R dwr[3][3];
             load_slots<N>(gW, tid, dwr);
@@ -710,7 +713,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         // each thread overwrites only its own point's slots, which only it read
         if (active) store_slots<N>(gW, tid, Q);
         __syncthreads();
-        backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TR, gW, vW, bW);
+        backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TR, gW, vW, bW, sL);
     }
 }
 

@@ -53,6 +53,10 @@ struct KParams {
     // every (cell, local node), ne x n^3, and the 8 vertex ids of every cell
     const int* conn;
     const int* ev;
+    // general meshes: distinct nodes of each workgroup's cells (cells x n^3
+    // slots per group, -1 padded) and each cell node's slot
+    const int* gnodes;
+    const unsigned short* lidx;
     double mu, lam;            // uniform material
     int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
 };

@@ -165,4 +165,45 @@ std::string number_hex_nodes(int64_t nv, int64_t ne, const int32_t* ev, int p, s
     return "";
 }
 
+namespace {
+// the low 21 bits of v spread to every third bit
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+}  // namespace
+
+void morton_order(int64_t nv, const double* xyz, int64_t ne, const int32_t* ev, std::vector<int32_t>& perm) {
+    double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+    for (int64_t v = 1; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], xyz[3 * v + d]);
+            hi[d] = std::max(hi[d], xyz[3 * v + d]);
+        }
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        uint64_t code = 0;
+        for (int d = 0; d < 3; ++d) {
+            double x = 0.0;
+            for (int v = 0; v < 8; ++v) x += xyz[3 * (int64_t)ev[8 * e + v] + d];
+            const double span = hi[d] - lo[d];
+            const double t = span > 0.0 ? (x / 8.0 - lo[d]) / span : 0.0;
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+            code |= spread3(q) << d;
+        }
+        key[e] = {code, (int32_t)e};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, int32_t>& a, const std::pair<uint64_t, int32_t>& b) {
+                         return a.first < b.first;
+                     });
+    perm.resize((size_t)ne);
+    for (int64_t e = 0; e < ne; ++e) perm[e] = key[e].second;
+}
+
 }  // namespace mfe

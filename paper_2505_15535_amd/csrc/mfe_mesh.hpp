@@ -24,4 +24,9 @@ namespace mfe {
 std::string number_hex_nodes(int64_t nv, int64_t ne, const int32_t* ev, int p, std::vector<int32_t>& conn,
                              int64_t& n_nodes);
 
+// perm[k] = the cell processed k-th: cells sorted (stably) by the Morton
+// code of their centroids (21 bits per axis over the vertices' bounding
+// box), so that consecutive cells are close in space.
+void morton_order(int64_t nv, const double* xyz, int64_t ne, const int32_t* ev, std::vector<int32_t>& perm);
+
 }  // namespace mfe
