@@ -8,7 +8,8 @@ before the timed region (they are built once per linearisation point; their
 build time is reported separately).  Every strategy is timed; the headline
 `value` is the fastest one.  Beside it, under "mixed": FP64 and FP32-sweep
 applies on the Q4 24^3 and Q6 12^3 boxes (and the headline box) with the
-error of the FP32 result against the FP64 one; under "hex": the apply on
+error of the FP32 result against the FP64 one; per strategy, "cold" times the apply with the caches flushed between applies;
+"cpu_csr" is the assembled-matrix product on the host cores; under "hex": the apply on
 general hexahedral meshes (the headline box given as one, and an unstructured
 mesh of the same size); under "newton": the twisted beam (64x16x16 Q2,
 lambda/mu = 100, 90 degrees in 10 load steps) solved to ||R|| <= 1e-8 with
@@ -137,6 +138,54 @@ def cpu_baseline(cfg, target_s: float = 12.0) -> dict:
             "sample": f"naive FP64 cell loop (explicit 81-entry tangent, numpy) over {len(cells)} of "
                       f"{mesh.n_elems} cells of {cfg.name} in {t_wall:.1f} s, scaled by the cell fraction",
             "host_threads": os.cpu_count()}
+
+
+def cpu_csr_baseline(nx: int = 10) -> dict:
+    """The assembled-matrix alternative the paper compares against (Sec.
+    3.2.2): the oracle's tangent assembled into CSR on a bounded box of the
+    headline workload's kind (nx^3 jittered Q2 cells, same material and
+    displacement recipe), then y = K w with the oracle's OpenMP CSR kernel on
+    all host cores, median of 10 products, reported as DoF/s.  The CSR
+    product's cost per DoF does not depend on the box size once the matrix
+    is larger than the host caches (here about 60 MB: a lower bound on the
+    per-DoF cost where the host cache holds the whole matrix)."""
+    import ctypes
+
+    import numpy as np
+    from oracle.fem import Problem
+    from oracle.mesh import BoxMesh
+    import synthetic
+
+    cfg = synthetic.get_config("box48_q2")
+    verts = synthetic.box_vertices(nx, nx, nx, (1.0, 1.0, 1.0), 0.1, np.random.default_rng(7))
+    u = synthetic.sine_displacement(nx, nx, nx, 2, cfg.amplitude, np.random.default_rng(8))
+    t0 = time.perf_counter()
+    K = Problem(BoxMesh(nx, nx, nx, 2, verts), cfg.mu, cfg.lam, chunk=256).assemble_tangent(u).tocsr()
+    t_asm = time.perf_counter() - t0
+    lib_path = os.path.join(ROOT, "oracle", "libcsr_spmv.so")
+    if not os.path.exists(lib_path):
+        raise RuntimeError("oracle/libcsr_spmv.so is not built (run the build step)")
+    lib = ctypes.CDLL(lib_path)
+    lib.csr_spmv.restype = ctypes.c_int
+    lib.csr_spmv.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5
+    indptr = np.ascontiguousarray(K.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(K.indices, dtype=np.int32)
+    data = np.ascontiguousarray(K.data, dtype=np.float64)
+    x = np.random.default_rng(9).standard_normal(K.shape[0])
+    y = np.empty_like(x)
+    times, threads = [], 1
+    for _ in range(11):
+        t0 = time.perf_counter()
+        threads = lib.csr_spmv(K.shape[0], indptr.ctypes.data, indices.ctypes.data, data.ctypes.data,
+                               x.ctypes.data, y.ctypes.data)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times[1:]))
+    n = K.shape[0]
+    return {"value": n / t / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle assembled CSR",
+            "sample": f"{nx}^3 jittered Q2 box, {n} DoF, {K.nnz} stored entries ({K.nnz / n:.0f} per row, "
+                      f"{(K.nnz * 12 + 8 * n) / 1e6:.0f} MB CSR); median of 10 OpenMP products; assembly "
+                      f"{t_asm:.1f} s (numpy, one core)",
+            "assembly_s": round(t_asm, 2), "spmv_ms": round(t * 1e3, 3)}
 
 
 # --------------------------------------------------------------------------- mixed precision
@@ -448,6 +497,9 @@ def main(argv=None):
     state_ms = (time.perf_counter() - t0) * 1e3
 
     results = {}
+    if strategies:
+        flush_src = torch.ones(1 << 26, dtype=torch.float64, device=dev)   # 512 MiB each
+        flush_dst = torch.empty_like(flush_src)
     for s in strategies:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -467,6 +519,15 @@ def main(argv=None):
         op.set_timing(False)
         if not np.isfinite(float(v.abs().max())):
             raise RuntimeError(f"non-finite result for strategy {s}")
+        # cold: a 1 GiB copy between applies evicts the L2s and the 256 MB
+        # Infinity Cache, so the vectors come from HBM as well (kernel time only)
+        op.set_timing(True)
+        for _ in range(10):
+            flush_dst.copy_(flush_src)
+            op.apply(w, out=v, strategy=s)
+        torch.cuda.synchronize()
+        cold_ms, _ = op.apply_kernel_ms()
+        op.set_timing(False)
         model = work_model(s, cfg.degree, op.n_dofs, op.n_qpoints, (cfg.nx + 1) * (cfg.ny + 1) * (cfg.nz + 1))
         results[s] = {
             "ms_per_step": round(step_ms, 5),
@@ -475,6 +536,7 @@ def main(argv=None):
             "kernel_launches_timed": n_ev,
             "cache_build_ms": round(build_ms, 3),
             "cache_mb": round(op.cache_bytes(s) / 1e6, 1),
+            "cold": {"kernel_ms": round(cold_ms, 5), "gdofs_kernel": round(op.n_dofs / (cold_ms * 1e-3) / 1e9, 4)},
             "roofline": roofline(model, kern_ms, measured_traffic(cfg.name, s)),
             "work_model": {k: (round(x, 3) if isinstance(x, float) else x) for k, x in model.items()},
         }
@@ -535,6 +597,8 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg)
+        print("[bench] timing the assembled-CSR product on the host cores", file=sys.stderr, flush=True)
+        line["cpu_csr"] = cpu_csr_baseline()
     text = json.dumps(line)
     print(text, flush=True)
     if args.out:

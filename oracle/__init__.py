@@ -30,6 +30,9 @@ linelast  textbook small-strain stiffness B^T D B (pin for the u = 0 limit)
 solver    Newton on the weak form with assembled tangent and direct solves
 net       the learned smoother's convolutional network: forward, loss,
           parameter gradients, Adam step, patch node map
+csr_spmv.c  y = A x for an assembled CSR matrix on all host cores (OpenMP):
+          the assembled-matrix baseline the benchmark's CPU leg times on the
+          oracle's assembled tangent (compiled by build_c.py)
 
 Every function is float64 unless it is fed complex128 input for the
 complex-step pins, in which case it works in complex128 throughout.
