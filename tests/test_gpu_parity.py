@@ -264,3 +264,52 @@ def test_error_paths(torch_dev):
     with pytest.raises(mfe.MfeError) as e:
         _op(torch_dev, cfg.nx, cfg.ny, cfg.nz, cfg.degree, bad, 1.0, 1.0)
     assert e.value.code == mfe.MFE_EJACOBIAN
+
+
+def test_zero_state_is_textbook_linear_elasticity(torch_dev):
+    """The degenerate state u = 0: every strategy gives the textbook
+    small-strain stiffness B^T D B with Lame constants (2 lambda, mu) (the
+    energy's lambda log^2 J term) times w, on a jittered box."""
+    from oracle import linelast
+    nx, ny, nz, p = 3, 2, 2, 2
+    verts = synthetic.box_vertices(nx, ny, nz, (1.0, 0.7, 0.9), 0.12, np.random.default_rng(61))
+    mesh = BoxMesh(nx, ny, nz, p, verts)
+    K0 = linelast.assemble(mesh, 2.0 * 10.0, 1.0)
+    W = np.random.default_rng(62).standard_normal((2, mesh.n_dofs))
+    op = _op(torch_dev, nx, ny, nz, p, verts, 1.0, 10.0)
+    got = _apply_all(torch_dev, op, np.zeros(mesh.n_dofs), W)
+    for s, V in got.items():
+        for k in range(2):
+            assert _rel(V[k], K0 @ W[k]) <= TOL, s
+
+
+def test_mesh_limits_are_refused(torch_dev):
+    """Sizes past 32-bit dof indices, degrees outside 1..6, empty meshes and
+    null arrays are refused before anything is read or allocated."""
+    import paper_2505_15535_amd as mfe
+    ctx = mfe.mfe_create(0)
+    try:
+        one = np.zeros(3 * 8)
+        for args in [(1000, 1000, 1000, 2), (1, 1, 1, 0), (1, 1, 1, 7), (0, 1, 1, 1)]:
+            with pytest.raises(mfe.MfeError) as e:
+                mfe.mfe_mesh_box(ctx, *args, one.ctypes.data)
+            assert e.value.code == mfe.MFE_EINVAL, args
+        with pytest.raises(mfe.MfeError) as e:
+            mfe.mfe_mesh_box(ctx, 1, 1, 1, 2, None)
+        assert e.value.code == mfe.MFE_EINVAL
+        cells = np.arange(8, dtype=np.int32)
+        with pytest.raises(mfe.MfeError) as e:
+            mfe.mfe_mesh_hex(ctx, 8, one.ctypes.data, 0, cells.ctypes.data, 2)
+        assert e.value.code == mfe.MFE_EINVAL
+        with pytest.raises(mfe.MfeError) as e:
+            mfe.mfe_mesh_hex(ctx, 8, one.ctypes.data, 1, cells.ctypes.data, 7)
+        assert e.value.code == mfe.MFE_EINVAL
+        assert mfe.mfe_n_dofs(ctx) == 0        # no mesh was set by any of them
+        # a degenerate (flat) cell is refused by the geometry check
+        flat = synthetic.box_vertices(1, 1, 1)
+        flat[:, 2] = 0.0
+        with pytest.raises(mfe.MfeError) as e:
+            mfe.mfe_mesh_box(ctx, 1, 1, 1, 1, np.ascontiguousarray(flat).ctypes.data)
+        assert e.value.code == mfe.MFE_EJACOBIAN
+    finally:
+        mfe.mfe_destroy(ctx)
