@@ -327,3 +327,41 @@ def test_gmg_single_level_is_a_direct_solve(torch_dev, prec, tol):
     op.gmg_setup(**smooth)
     z2 = op.gmg_apply(_to(torch_dev, r), **smooth).cpu().numpy()
     assert np.linalg.norm(z2 - ref) / np.linalg.norm(ref) > 1e-3
+
+
+def test_gmg_direct_coarse_falls_back_on_indefinite_level(torch_dev):
+    """At a state whose tangent is indefinite (smallest eigenvalue -0.03 on
+    the 2x1x1 box), the sweep inversion of the one-level hierarchy meets a
+    pivot <= 0 and the level is smoothed instead: set-up either reports the
+    indefinite level or succeeds with a preconditioner that is not the exact
+    inverse; nothing else is left changed (a later SPD state is solved
+    exactly again)."""
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz = 2, 1, 1
+    verts = synthetic.box_vertices(nx, ny, nz, (1.0, 0.8, 0.7))
+    mesh = BoxMesh(nx, ny, nz, 2, verts)
+    left = np.where(mesh.node_positions()[:, 0] < 1e-12)[0]
+    cdofs = (3 * left[:, None] + np.arange(3)).ravel()
+    P = Problem(mesh, 1.0, 10.0, constrained_dofs=cdofs)
+    u_bad = synthetic.sine_displacement(nx, ny, nz, 2, 0.01, synthetic.rng_for(95, 1))
+    K_bad = P.assemble_tangent(u_bad)
+    assert np.linalg.eigvalsh(K_bad.toarray()).min() < 0.0
+    r = synthetic.random_vectors(mesh.n_dofs, 1, synthetic.rng_for(95, 2))[0]
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, 10.0, device=0)
+    op.set_constraints(cdofs)
+    opts = dict(strategy="t2", mg_levels=1, coarse_direct=1)
+    op.set_state(_to(torch_dev, u_bad))
+    try:
+        op.gmg_setup(**opts)
+        z = op.gmg_apply(_to(torch_dev, r), **opts).cpu().numpy()
+        exact = spla.spsolve(K_bad.tocsc(), r)
+        assert np.linalg.norm(z - exact) / np.linalg.norm(exact) > 1e-3
+    except mfe.MfeError as e:
+        assert e.code in (mfe.MFE_ENOTCONV, mfe.MFE_EJACOBIAN)
+    u_ok = synthetic.sine_displacement(nx, ny, nz, 2, 0.002, synthetic.rng_for(95, 1))
+    op.set_state(_to(torch_dev, u_ok))
+    op.gmg_setup(**opts)
+    z = op.gmg_apply(_to(torch_dev, r), **opts).cpu().numpy()
+    ref = spla.spsolve(P.assemble_tangent(u_ok).tocsc(), r)
+    assert np.linalg.norm(z - ref) / np.linalg.norm(ref) <= 1e-10
