@@ -206,8 +206,10 @@ def time_applies(op, w, v, strategy, precision, steps, warmup):
 
 
 def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
-    """FP64 and FP32-sweep applies of one workload; error of the FP32 result
-    against the FP64 one (the FP64 path itself matches the oracle to 1e-12)."""
+    """FP64 applies and applies with FP32 vectors and caches whose sweeps run in
+    FP32 on the vector ALUs, or on the matrix cores as bf16x3 (three-piece
+    split, FP32-accurate) or bf16 (one product); error of each result against
+    the FP64 one (the FP64 path itself matches the oracle to 1e-12)."""
     import numpy as np
     import torch
 
@@ -220,24 +222,28 @@ def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
     op.set_state(torch.from_numpy(cfg.displacement()).to(dev))
     w64 = torch.from_numpy(cfg.test_vector(0).astype(np.float32).astype(np.float64)).to(dev)
     w32 = w64.float()
-    v64, v32 = torch.empty_like(w64), torch.empty_like(w32)
+    v64 = torch.empty_like(w64)
     nv = (cfg.nx + 1) * (cfg.ny + 1) * (cfg.nz + 1)
     out = {"n_dofs": op.n_dofs, "degree": cfg.degree, "description": cfg.description}
     for s in strategies:
         rec = {}
-        for prec, w, v, elem in (("fp64", w64, v64, 8), ("fp32", w32, v32, 4)):
+        for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+            w, elem = (w64, 8) if prec == "fp64" else (w32, 4)
+            v = v64 if prec == "fp64" else torch.empty_like(w32)
             op.build_cache(s, precision=prec)
             step_ms, kern_ms = time_applies(op, w, v, s, prec, steps, warmup)
             model = work_model(s, cfg.degree, op.n_dofs, op.n_qpoints, nv, elem)
             rl = roofline(model, kern_ms, None, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS)
             rec[prec] = {"ms_per_step": round(step_ms, 5), "kernel_ms": round(kern_ms, 5),
                          "gdofs": round(op.n_dofs / (step_ms * 1e-3) / 1e9, 4), "roofline": rl}
-        err = float(torch.linalg.norm(v32.double() - v64) / torch.linalg.norm(v64))
-        rec["fp32_rel_err_vs_fp64"] = err
-        rec["speedup_fp32"] = round(rec["fp64"]["ms_per_step"] / rec["fp32"]["ms_per_step"], 3)
+            if prec != "fp64":
+                err = float(torch.linalg.norm(v.double() - v64) / torch.linalg.norm(v64))
+                rec[prec]["rel_err_vs_fp64"] = err
+                rec[prec]["speedup_vs_fp64"] = round(rec["fp64"]["ms_per_step"] / step_ms, 3)
         out[s] = rec
-        print(f"[bench] mixed {name} {s}: fp64 {rec['fp64']['gdofs']:.2f} GDoF/s, fp32 {rec['fp32']['gdofs']:.2f} "
-              f"GDoF/s, rel err {err:.1e}", file=sys.stderr, flush=True)
+        print(f"[bench] mixed {name} {s}: " + ", ".join(
+            f"{p} {rec[p]['gdofs']:.2f} GDoF/s" + (f" (err {rec[p]['rel_err_vs_fp64']:.1e})" if p != "fp64" else "")
+            for p in ("fp64", "fp32", "bf16x3", "bf16")), file=sys.stderr, flush=True)
     op.close()
     return out
 

@@ -87,7 +87,16 @@ typedef enum mfe_strategy {
  *                F, J, log J and rounded once, all products FP32); on-the-fly
  *                strategies keep u, F, J, log J and the point-wise response in
  *                FP64 and round the result to FP32 before the contraction.
- *   MFE_SF_BF16, MFE_SF_BF16X3  not built: MFE_EUNSUPPORTED. */
+ *   MFE_SF_BF16  as MFE_SF_FP32 (float w and v, the FP32 cache of
+ *                mfe_build_cache_fp32), but the sum-factorization sweeps of w
+ *                and the test contraction run on the matrix cores: 16x16x16
+ *                bf16 products with FP32 accumulation, both operands rounded
+ *                to bf16 (relative error of v about 5e-3 .. 1e-2).
+ *   MFE_SF_BF16X3  the same products with both operands split into three
+ *                bf16 pieces and the six piece products of order <= 2
+ *                accumulated: the accuracy of the FP32 sweeps.
+ *   The two matrix-core precisions are built for structured boxes
+ *   (mfe_mesh_box); on a general mesh they return MFE_EUNSUPPORTED. */
 typedef enum mfe_precision {
     MFE_FP64 = 0,
     MFE_SF_FP32 = 1,

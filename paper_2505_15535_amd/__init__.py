@@ -447,22 +447,24 @@ class Operator:
         mfe_set_state(self.ctx, _dev_f64(u, self.n_dofs, "u"), _stream_handle(stream))
 
     def build_cache(self, strategy, stream=None, precision="fp64"):
-        """Per-point data of `strategy` for applies of `precision` ("fp64" or "fp32")."""
+        """Per-point data of `strategy` for applies of `precision` ("fp64", or
+        "fp32" / "bf16" / "bf16x3", which read the FP32 cache)."""
         prec = PRECISIONS.get(precision, precision)
-        build = mfe_build_cache_fp32 if prec == MFE_SF_FP32 else mfe_build_cache
+        build = mfe_build_cache_fp32 if prec in (MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3) else mfe_build_cache
         build(self.ctx, STRATEGIES.get(strategy, strategy), _stream_handle(stream))
 
     def cache_bytes(self, strategy):
         return mfe_cache_bytes(self.ctx, STRATEGIES.get(strategy, strategy))
 
     def apply(self, w, out=None, strategy="otf", precision=MFE_FP64, stream=None):
-        """out = K(u) w.  precision "fp64" (float64 tensors) or "fp32" (float32
-        tensors: FP32 sweeps, see mfe_precision)."""
+        """out = K(u) w.  precision "fp64" (float64 tensors), or "fp32", "bf16",
+        "bf16x3" (float32 tensors: FP32 caches and vectors, the sweeps of w on
+        the vector ALUs in FP32 or on the matrix cores, see mfe_precision)."""
         import torch
         prec = PRECISIONS.get(precision, precision)
         if out is None:
             out = torch.empty_like(w)
-        if prec == MFE_SF_FP32:
+        if prec in (MFE_SF_FP32, MFE_SF_BF16, MFE_SF_BF16X3):
             wp, op = _dev_tensor(w, self.n_dofs, "w", torch.float32), _dev_tensor(out, self.n_dofs, "out", torch.float32)
         else:
             wp, op = _dev_f64(w, self.n_dofs, "w"), _dev_f64(out, self.n_dofs, "out")

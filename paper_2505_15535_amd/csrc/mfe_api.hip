@@ -876,12 +876,12 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     c->err.clear();
     if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
     if (!w || !v) return fail(c, MFE_EINVAL, "null vector");
-    if (precision != MFE_FP64 && precision != MFE_SF_FP32) {
-        if (precision >= MFE_SF_BF16 && precision <= MFE_SF_BF16X3)
-            return fail(c, MFE_EUNSUPPORTED, "BF16 sweeps are not built");
-        return fail(c, MFE_EINVAL, "unknown precision");
-    }
-    const bool fp32 = precision == MFE_SF_FP32;
+    if (precision < MFE_FP64 || precision > MFE_SF_BF16X3) return fail(c, MFE_EINVAL, "unknown precision");
+    // BF16 / BF16X3: the FP32 path (float vectors, FP32 caches) with the
+    // sweeps of w on the matrix cores
+    const bool fp32 = precision != MFE_FP64;
+    const int sweep = precision == MFE_SF_BF16 ? 1 : precision == MFE_SF_BF16X3 ? 3 : 0;
+    if (sweep && c->hex) return fail(c, MFE_EUNSUPPORTED, "matrix-core sweeps are built for structured boxes");
     const int64_t esize = fp32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
     if (overlaps(w, v, c->n_dofs * esize)) return fail(c, MFE_EINVAL, "w and v overlap");
     int mode;
@@ -945,7 +945,7 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         }
         MFE_HIP(c, hipEventRecord(c->ev_start[c->ev_used], s));
     }
-    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32));
+    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep));
     if (timed) {
         MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
         c->ev_used++;

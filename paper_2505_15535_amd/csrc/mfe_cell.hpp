@@ -314,6 +314,19 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
     __syncthreads();
 }
 
+// The brick's summed node values (sBrick, made visible by a barrier) added to
+// dst: plain stores for nodes inside the brick, FP64/FP32 atomics on its faces.
+template <int N, bool HX, typename R>
+__device__ __forceinline__ void brick_scatter(R* __restrict__ dst, const BrickMap<N, HX>& bm, const R* sBrick) {
+#pragma unroll
+    for (int k = 0; k < Geo<N, HX>::GPT; ++k) {
+        if (!(bm.exists >> k & 1u)) continue;
+        const R val = sBrick[threadIdx.x + k * Geo<N, HX>::NT];
+        if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
+        else dst[bm.dof[k]] = val;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Backward sweeps: on entry slot d of sG holds Q[c][d] at every point (made
 // visible by a barrier) and sBrick is zero.  Adds
@@ -400,13 +413,234 @@ __device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const Brick
         for (int i = 0; i < N; ++i) atomicAdd(sBrick + brick_node<N, HX>(L, i, j, k, sL), y[i]);
     }
     __syncthreads();
+    brick_scatter<N, HX>(dst, bm, sBrick);
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps of the w field on the matrix cores (MFE_SF_BF16: SW = 1,
+// MFE_SF_BF16X3: SW = 3).  A sweep stage is a batch of small dense products
+// out[q] = sum_k M[q][k] in[k], one per 1D line, done as 16 x 16 x 16 bf16
+// matrix-core products with FP32 accumulation.  A column of the 16 x 16 B
+// operand stacks LPC = floor(16 / n) lines (rows j n .. j n + n - 1 hold line
+// j), and A is the block-diagonal matrix of LPC copies of M, so one product
+// handles 16 LPC lines and the C operand holds the outputs in the same row
+// layout; tiles of 16 LPC lines are dealt to the wavefronts.  With SW = 3
+// both operands are split into three bf16 pieces, x = x0 + x1 + x2 (8
+// significant bits each, so the FP32 value exactly), and the six products of
+// total order <= 2 are accumulated, smallest first: about FP32 accuracy.
+// With SW = 1 a single bf16 product (unit roundoff 2^-9).  The LDS layouts and
+// the addresses of every stage are those of the vector-ALU sweeps.
+// ---------------------------------------------------------------------------
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float((uint32_t)(unsigned short)h << 16); }
+
+// x = p[0] + ... + p[NP-1], each piece rounded to the nearest bf16
+template <int NP>
+__device__ __forceinline__ void split_bf16(float x, short (&p)[NP]) {
 #pragma unroll
-    for (int k = 0; k < G::GPT; ++k) {
-        if (!(bm.exists >> k & 1u)) continue;
-        const R val = sBrick[threadIdx.x + k * G::NT];
-        if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
-        else dst[bm.dof[k]] = val;
+    for (int i = 0; i < NP; ++i) {
+        p[i] = bf16_rne(x);
+        if (i + 1 < NP) x -= bf16_value(p[i]);
     }
+}
+
+// c += sum over i + j < NP of A_i B_j, products of the highest order first
+template <int NP>
+__device__ __forceinline__ f32x4_t mfma_pieces(const bf16x4_t (&a)[NP], const bf16x4_t (&b)[NP], f32x4_t c) {
+#pragma unroll
+    for (int o = NP - 1; o >= 0; --o)
+#pragma unroll
+        for (int i = 0; i <= o; ++i) c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[o - i], c, 0, 0, 0);
+    return c;
+}
+
+// this lane's pieces of the block-diagonal A operand: lane l holds
+// A[l % 16][4 (l / 16) + r], i.e. M[i % n][k % n] when rows i and k belong to
+// the same stacked line (i / n == k / n < LPC), else 0
+template <int N, int NP, typename MatFn>
+__device__ __forceinline__ void a_fragment(MatFn mat, bf16x4_t (&a)[NP]) {
+    constexpr int LPC = 16 / N;
+    const int l = threadIdx.x & 63, i = l & 15, ji = i / N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = 4 * (l >> 4) + r, jk = k / N;
+        short pc[NP];
+        split_bf16<NP>(ji == jk && ji < LPC ? mat(i - N * ji, k - N * jk) : 0.0f, pc);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) a[p][r] = pc[p];
+    }
+}
+
+// the B pieces of one input: rows 4 (l / 16) + r of this lane's column
+template <int N, int NP, typename In>
+__device__ __forceinline__ void b_fragment(In in, const Line& L0, const Line& L1, int j0, bf16x4_t (&b)[NP]) {
+    constexpr int LPC = 16 / N;
+    const int r0 = 4 * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = (r0 + r) / N, k = r0 + r - N * j;
+        const Line& L = j == j0 ? L0 : L1;
+        short pc[NP];
+        split_bf16<NP>(j < LPC && L.valid ? in(L, k) : 0.0f, pc);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) b[p][r] = pc[p];
+    }
+}
+
+template <int N, typename Out>
+__device__ __forceinline__ void c_store(Out out, const Line& L0, const Line& L1, int j0, const f32x4_t& c) {
+    constexpr int LPC = 16 / N;
+    const int r0 = 4 * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = (r0 + r) / N, q = r0 + r - N * j;
+        const Line& L = j == j0 ? L0 : L1;
+        if (j < LPC && L.valid) out(L, q, c[r]);
+    }
+}
+
+enum { MF_ONE = 0, MF_SUM = 1, MF_DUAL = 2 };
+
+// One stage over every line L of the brick (in*(L, k) read for k < n, out*(L,
+// q) written for q < n):
+//   MF_ONE   out1 = M1 in1
+//   MF_SUM   out1 = M1 in1 + M2 in2
+//   MF_DUAL  out1 = M1 in1, out2 = M2 in1
+// A lane's four rows span at most two stacked lines (n >= 2), L0 and L1; the
+// products run with every lane of the wavefront active.
+template <int N, bool HX, int NP, int KIND, typename M1, typename I1, typename M2, typename I2, typename O1,
+          typename O2>
+__device__ __forceinline__ void mfma_stage(const BrickPos& bp, M1 mat1, I1 in1, M2 mat2, I2 in2, O1 out1, O2 out2) {
+    using G = Geo<N, HX>;
+    constexpr int LPC = 16 / N, NW = G::NT / 64, TILES = (G::TASKS + 16 * LPC - 1) / (16 * LPC);
+    bf16x4_t a1[NP], a2[NP];
+    a_fragment<N, NP>(mat1, a1);
+    if constexpr (KIND != MF_ONE) a_fragment<N, NP>(mat2, a2);
+    const int l = threadIdx.x & 63, j0 = 4 * (l >> 4) / N;
+    for (int tile = threadIdx.x >> 6; tile < TILES; tile += NW) {
+        const int t0 = (tile * 16 + (l & 15)) * LPC + j0;
+        const Line L0 = line_of<N, HX>(t0, bp), L1 = line_of<N, HX>(t0 + 1, bp);
+        bf16x4_t b1[NP];
+        b_fragment<N, NP>(in1, L0, L1, j0, b1);
+        f32x4_t c1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (KIND == MF_SUM) {
+            bf16x4_t b2[NP];
+            b_fragment<N, NP>(in2, L0, L1, j0, b2);
+            c1 = mfma_pieces<NP>(a2, b2, c1);
+        }
+        c1 = mfma_pieces<NP>(a1, b1, c1);
+        if constexpr (KIND == MF_DUAL) {
+            f32x4_t c2 = {0.0f, 0.0f, 0.0f, 0.0f};
+            c2 = mfma_pieces<NP>(a2, b1, c2);
+            c_store<N>(out2, L0, L1, j0, c2);
+        }
+        c_store<N>(out1, L0, L1, j0, c1);
+    }
+}
+
+// Dense 1D matrices of the sweeps (row = output index): S, the collocated
+// derivative D, D S, and the transposes St, Dt, St Dt.
+template <int N>
+struct MfmaMats {
+    float S[N][N], D[N][N], DS[N][N], St[N][N], Dt[N][N], StDt[N][N];
+};
+
+// the matrix-core counterparts of forward_sweeps / backward_sweeps for the
+// w field (FP32 in LDS)
+template <int N, bool HX, int NP>
+__device__ __forceinline__ void forward_sweeps_mfma(const BrickPos& bp, const MfmaMats<N>& MM, float* sG, float* sV,
+                                                    float* sBrick, const unsigned short* sL) {
+    using G = Geo<N, HX>;
+    constexpr int N2 = G::N2;
+    auto none = [](int, int) { return 0.0f; };
+    auto no_in = [](const Line&, int) { return 0.0f; };
+    auto no_out = [](const Line&, int, float) {};
+    auto S = [&](int q, int k) { return MM.S[q][k]; };
+    auto D = [&](int q, int k) { return MM.D[q][k]; };
+    auto DS = [&](int q, int k) { return MM.DS[q][k]; };
+    // x: node x-rows -> slot 0 at (qx, j, k)
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, S, [&](const Line& L, int k) { return sBrick[brick_node<N, HX>(L, k, L.a, L.b, sL)]; }, none, no_in,
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * q] = v; }, no_out);
+    __syncthreads();
+    for (int e = threadIdx.x; e < G::BRICK; e += G::NT) sBrick[e] = 0.0f;  // for the backward accumulation
+    // y: slot 0 -> slot 1
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, S, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * k]; }, none, no_in,
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * q + 1] = v; }, no_out);
+    __syncthreads();
+    // z: slot 1 -> values (S, into sV) and their z-derivative (D S, slot 2)
+    mfma_stage<N, HX, NP, MF_DUAL>(
+        bp, S, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * k + 1]; }, DS,
+        no_in, [&](const Line& L, int q, float v) { sV[(gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * q) / 3] = v; },
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * q + 2] = v; });
+    __syncthreads();
+    // x- and y-derivatives of the values -> slots 0 and 1
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, D, [&](const Line& L, int k) { return sV[(gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * k) / 3]; },
+        none, no_in,
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * q] = v; }, no_out);
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, D, [&](const Line& L, int k) { return sV[(gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * k) / 3]; },
+        none, no_in,
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * q + 1] = v; }, no_out);
+    __syncthreads();
+}
+
+template <int N, bool HX, int NP>
+__device__ __forceinline__ void backward_sweeps_mfma(float* __restrict__ dst, const BrickPos& bp,
+                                                     const BrickMap<N, HX>& bm, const MfmaMats<N>& MM, float* sG,
+                                                     float* sV, float* sBrick, const unsigned short* sL) {
+    using G = Geo<N, HX>;
+    constexpr int N2 = G::N2;
+    auto none = [](int, int) { return 0.0f; };
+    auto no_in = [](const Line&, int) { return 0.0f; };
+    auto no_out = [](const Line&, int, float) {};
+    auto St = [&](int q, int k) { return MM.St[q][k]; };
+    auto Dt = [&](int q, int k) { return MM.Dt[q][k]; };
+    auto StDt = [&](int q, int k) { return MM.StDt[q][k]; };
+    // transposed x- and y-derivatives, in place in slots 0 and 1 (a column's
+    // lines are read into registers before the product and written after it,
+    // all by one wavefront)
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, Dt, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * k]; }, none,
+        no_in, [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * q] = v; },
+        no_out);
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, Dt, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * k + 1]; }, none,
+        no_in, [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * q + 1] = v; },
+        no_out);
+    __syncthreads();
+    // z: St Dt (slot 2) + St (slot 0 + slot 1) -> sV at (qx, qy, k)
+    mfma_stage<N, HX, NP, MF_SUM>(
+        bp, StDt, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * k + 2]; }, St,
+        [&](const Line& L, int k) {
+            const int b = gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * k;
+            return sG[b] + sG[b + 1];
+        },
+        [&](const Line& L, int q, float v) { sV[(gofs<N>(L.lc, L.a + N * L.b, L.c) + 9 * N2 * q) / 3] = v; },
+        no_out);
+    __syncthreads();
+    // transposed y-interpolation: sV at (qx, qy, k) -> slot 0 at (qx, j, k)
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, St, [&](const Line& L, int k) { return sV[(gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * k) / 3]; },
+        none, no_in,
+        [&](const Line& L, int q, float v) { sG[gofs<N>(L.lc, L.a + N2 * L.b, L.c) + 9 * N * q] = v; }, no_out);
+    __syncthreads();
+    // transposed x-interpolation, summed into the brick's nodes in LDS
+    mfma_stage<N, HX, NP, MF_ONE>(
+        bp, St, [&](const Line& L, int k) { return sG[gofs<N>(L.lc, N * (L.a + N * L.b), L.c) + 9 * k]; }, none,
+        no_in,
+        [&](const Line& L, int q, float v) { atomicAdd(sBrick + brick_node<N, HX>(L, q, L.a, L.b, sL), v); },
+        no_out);
+    __syncthreads();
+    brick_scatter<N, HX>(dst, bm, sBrick);
 }
 
 template <int N, typename R>
@@ -479,9 +713,12 @@ __device__ __forceinline__ R* cache_out_of(const KParams& p) {
     if constexpr (std::is_same_v<R, float>) return p.cache_out32; else return p.cache_out;
 }
 
-template <int N, int MODE, typename R, bool HX>
+// SW: sweeps of the w field on the vector ALUs (0) or on the matrix cores
+// with one (1) or three (3) bf16 pieces per operand (R = float only).
+template <int N, int MODE, typename R, bool HX, int SW = 0>
 __global__ __launch_bounds__((Geo<N, HX>::NT)) __attribute__((amdgpu_waves_per_eu(MFE_MIN_WAVES_PER_EU)))
-void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
+void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, const MfmaMats<N> MM) {
+    static_assert(SW == 0 || std::is_same_v<R, float>, "matrix-core sweeps take FP32 operands");
     using G = Geo<N, HX>;
     constexpr int N3 = G::N3;
     using MI = ModeInfo<MODE>;
@@ -672,7 +909,8 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         // sBrick was last read before the forward sweeps' first barrier
         brick_store<N, HX>(bW, wb);
         __syncthreads();
-        forward_sweeps<N, HX>(bp, TR, gW, vW, bW, true, sL);
+        if constexpr (SW > 0) forward_sweeps_mfma<N, HX, SW>(bp, MM, gW, vW, bW, sL);
+        else forward_sweeps<N, HX>(bp, TR, gW, vW, bW, true, sL);
         if (active) {
             R dwr[3][3];
             load_slots<N>(gW, tid, dwr);
@@ -713,7 +951,8 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR) {
         // each thread overwrites only its own point's slots, which only it read
         if (active) store_slots<N>(gW, tid, Q);
         __syncthreads();
-        backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TR, gW, vW, bW, sL);
+        if constexpr (SW > 0) backward_sweeps_mfma<N, HX, SW>(v_of<R>(p), bp, bm, MM, gW, vW, bW, sL);
+        else backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TR, gW, vW, bW, sL);
     }
 }
 
@@ -924,21 +1163,70 @@ static Tables<N, float> to_float(const Tables<N>& T) {
     return F;
 }
 
-template <int N, int MODE, typename R, bool HX>
-static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream) {
+template <int N>
+static MfmaMats<N> make_mfma_mats(const Tables1D& t) {
+    MfmaMats<N> M;
+    for (int q = 0; q < N; ++q)
+        for (int i = 0; i < N; ++i) {
+            double ds = 0.0, stdt = 0.0;
+            for (int l = 0; l < N; ++l) {
+                ds += t.D[q][l] * t.S[l][i];    // (D S)[q][i]
+                stdt += t.S[l][q] * t.D[i][l];  // (St Dt)[q][i]
+            }
+            M.S[q][i] = (float)t.S[q][i];
+            M.D[q][i] = (float)t.D[q][i];
+            M.St[q][i] = (float)t.S[i][q];
+            M.Dt[q][i] = (float)t.D[i][q];
+            M.DS[q][i] = (float)ds;
+            M.StDt[q][i] = (float)stdt;
+        }
+    return M;
+}
+
+template <int N, int MODE, typename R, bool HX, int SW = 0>
+static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream,
+                            const MfmaMats<N>& MM = MfmaMats<N>{}) {
     const int nb = p.nbx * p.nby * p.nbz;
     if constexpr (std::is_same_v<R, float>) {
         const Tables<N, float> TF = to_float<N>(T);
-        hipLaunchKernelGGL((cell_kernel<N, MODE, float, HX>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, TF);
+        hipLaunchKernelGGL((cell_kernel<N, MODE, float, HX, SW>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, TF,
+                           MM);
     } else {
-        hipLaunchKernelGGL((cell_kernel<N, MODE, double, HX>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, T);
+        hipLaunchKernelGGL((cell_kernel<N, MODE, double, HX>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, T,
+                           MM);
     }
     return hipGetLastError();
 }
 
+// the apply modes with matrix-core sweeps of the w field (boxes)
+template <int N, int SW>
+static hipError_t launch_mfma_n(int mode, const Tables<N>& T, const MfmaMats<N>& MM, const KParams& p,
+                                hipStream_t s) {
+    switch (mode) {
+        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float, false, SW>(T, p, s, MM);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int N, bool HX>
-static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s) {
+static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s, int sweep = 0) {
     const Tables<N> T = make_tables<N>(t);
+    if (sweep != 0) {  // matrix-core sweeps: FP32 vectors and caches, structured boxes
+        if constexpr (HX) {
+            return hipErrorInvalidValue;
+        } else {
+            if (!fp32) return hipErrorInvalidValue;
+            const MfmaMats<N> MM = make_mfma_mats<N>(t);
+            if (sweep == 1) return launch_mfma_n<N, 1>(mode, T, MM, p, s);
+            if (sweep == 3) return launch_mfma_n<N, 3>(mode, T, MM, p, s);
+            return hipErrorInvalidValue;
+        }
+    }
     if (fp32) {
         switch (mode) {
             case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, HX>(T, p, s);

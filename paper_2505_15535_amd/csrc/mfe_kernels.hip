@@ -59,16 +59,17 @@ hipError_t launch_dense_tangent(const Tables1D& t, const KParams& p, double* A, 
     }
 }
 
-hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32) {
+hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32,
+                              int sweep) {
     if (p.ne <= 0) return hipSuccess;
-    if (p.conn) return launch_cell_kernel_hex(mode, t, p, stream, fp32);
+    if (p.conn) return sweep ? hipErrorInvalidValue : launch_cell_kernel_hex(mode, t, p, stream, fp32);
     switch (t.n) {
-        case 2: return launch_n<2, false>(mode, fp32, t, p, stream);
-        case 3: return launch_n<3, false>(mode, fp32, t, p, stream);
-        case 4: return launch_n<4, false>(mode, fp32, t, p, stream);
-        case 5: return launch_n<5, false>(mode, fp32, t, p, stream);
-        case 6: return launch_n<6, false>(mode, fp32, t, p, stream);
-        case 7: return launch_n<7, false>(mode, fp32, t, p, stream);
+        case 2: return launch_n<2, false>(mode, fp32, t, p, stream, sweep);
+        case 3: return launch_n<3, false>(mode, fp32, t, p, stream, sweep);
+        case 4: return launch_n<4, false>(mode, fp32, t, p, stream, sweep);
+        case 5: return launch_n<5, false>(mode, fp32, t, p, stream, sweep);
+        case 6: return launch_n<6, false>(mode, fp32, t, p, stream, sweep);
+        case 7: return launch_n<7, false>(mode, fp32, t, p, stream, sweep);
         default: return hipErrorInvalidValue;
     }
 }

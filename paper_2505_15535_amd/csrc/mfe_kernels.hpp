@@ -84,8 +84,10 @@ void hex_group_shape(int n, int* cells, int* points_per_group);
 // Launch the cell kernel of `mode` for degree p = n-1 (n in 2..7).  With
 // fp32 the w/v vectors (w32, v32), the T2/T4 caches (cache32, cache_out32)
 // and the sweeps of w are FP32; only the apply and T2/T4 build modes exist so.
+// sweep = 1 or 3: the FP32 apply modes with the w-field sweeps on the matrix
+// cores (one or three bf16 pieces per operand; structured boxes only).
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream,
-                              bool fp32 = false);
+                              bool fp32 = false, int sweep = 0);
 // The general-mesh instantiations (p.conn != null), reached through
 // launch_cell_kernel and launch_diagonal.
 hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32);

@@ -175,6 +175,12 @@ def test_hex_unsupported_paths(torch_dev):
     with pytest.raises(mfe.MfeError) as e:
         op.gmg_setup()
     assert e.value.code == mfe.MFE_EUNSUPPORTED
+    torch, dev = torch_dev
+    for prec in ("bf16", "bf16x3"):          # matrix-core sweeps: structured boxes only
+        op.build_cache("t2", precision=prec)
+        with pytest.raises(mfe.MfeError) as e:
+            op.apply(torch.zeros(op.n_dofs, dtype=torch.float32, device=dev), strategy="t2", precision=prec)
+        assert e.value.code == mfe.MFE_EUNSUPPORTED
     bad = c.copy()
     bad[0, [0, 1]] = bad[0, [1, 0]]          # an inverted cell
     with pytest.raises(mfe.MfeError) as e:
