@@ -133,8 +133,8 @@ def test_patch_gather_scatter_and_invariants(torch_dev):
     assert cnt.max() == 2 and cnt.min() == 1
 
 
-def test_learned_correction_trains_and_is_judged_by_cg(torch_dev):
-    """Train on residuals from two load paths of a 16x8x8 beam and judge on a
+def test_learned_correction_trains_and_is_measured_by_cg(torch_dev):
+    """Train on residuals from two load paths of a 16x8x8 beam and evaluate on a
     held-out path (lambda = 100, 60 degrees): the energy of the error the
     V-cycle leaves must drop on held-out residuals; CG with the correction
     must reach the same tolerance with a true residual to match; the

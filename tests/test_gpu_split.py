@@ -61,6 +61,11 @@ def test_split_apply_parity(torch_dev, p, shape):
         v32 = op.apply(_to(torch_dev, W[0], np.float32), strategy=s, precision="fp32").cpu().numpy()
         ref32 = P.apply_naive(u, W[0].astype(np.float32).astype(np.float64))
         assert _rel(v32.astype(np.float64), ref32) <= 1e-5, (s, p)
+        # the matrix-core sweeps read the same FP32 cache (bounds derived in test_gpu_bf16)
+        for prec, lo, hi in (("bf16x3", 0.0, 1e-5), ("bf16", 1e-4, 3e-2)):
+            vb = op.apply(_to(torch_dev, W[0], np.float32), strategy=s, precision=prec).cpu().numpy()
+            e = _rel(vb.astype(np.float64), ref32)
+            assert lo < e <= hi, (s, p, prec, e)
     # residual and energy of the split law
     r = op.residual(_to(torch_dev, u)).cpu().numpy()
     assert _rel(r, P.residual(u)) <= TOL
