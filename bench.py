@@ -77,6 +77,10 @@ def work_model(strategy: str, degree: int, n_dofs: int, n_q: int, n_vertices: in
 
 
 FP32_PEAK_TFLOPS = 157.3      # vector FP32
+# Kernel durations come from every TIMING_EVERY-th launch of the timed steps:
+# a timestamped dispatch costs a few microseconds of stream time, which would
+# otherwise be added to every step.
+TIMING_EVERY = 10
 
 
 def roofline(model: dict, kernel_ms: float, traffic, alu_peak: float = FP64_PEAK_TFLOPS) -> dict:
@@ -193,7 +197,7 @@ def time_applies(op, w, v, strategy, precision, steps, warmup):
     import torch
     for _ in range(warmup):
         op.apply(w, out=v, strategy=strategy, precision=precision)
-    op.set_timing(True)
+    op.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -514,7 +518,7 @@ def main(argv=None):
         build_ms = (time.perf_counter() - t0) * 1e3
         for _ in range(args.warmup):
             op.apply(w, out=v, strategy=s)
-        op.set_timing(True)
+        op.set_timing(TIMING_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):

@@ -384,11 +384,16 @@ int mfe_axpby(mfe_ctx* ctx, double a, const double* x_dev, double b, double* y_d
  * it is stale.  d_dev: device array of n_dofs doubles.  Asynchronous. */
 int mfe_diagonal(mfe_ctx* ctx, double* d_dev, void* stream);
 
-/* Average duration in milliseconds of the last `n` launches of the apply
- * kernel recorded with timing enabled, measured by HIP events recorded
- * around the kernel on the launch stream; -1 if none.  Timing is enabled by
- * mfe_set_timing(ctx, 1) and costs two event records per apply. */
-int mfe_set_timing(mfe_ctx* ctx, int enabled);
+/* Kernel timing of mfe_apply_tangent.  mfe_set_timing(ctx, every) records
+ * the apply kernel of every `every`-th call from now on (1: every call, 0:
+ * off; < 0: MFE_EINVAL) and forgets earlier records.  A recorded launch
+ * carries a start and a stop HIP event that its dispatch packet records on the
+ * launch stream (no extra commands between the kernels); a timestamped
+ * dispatch still costs a few microseconds of stream time, hence the interval.
+ * mfe_apply_kernel_ms returns the average duration in milliseconds of the
+ * recorded launches and their number in *count_out (may be NULL); -1 and 0 if
+ * none.  Synchronizes with the recorded events. */
+int mfe_set_timing(mfe_ctx* ctx, int every);
 double mfe_apply_kernel_ms(mfe_ctx* ctx, int* count_out);
 
 /* ---------------------------------------------------------------------------

@@ -329,8 +329,8 @@ def mfe_diagonal(ctx, d_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_diagonal(ctx, d_dev_ptr, stream))
 
 
-def mfe_set_timing(ctx, enabled: bool):
-    return _check(ctx, _lib.mfe_set_timing(ctx, 1 if enabled else 0))
+def mfe_set_timing(ctx, every):
+    return _check(ctx, _lib.mfe_set_timing(ctx, int(every)))
 
 
 def mfe_apply_kernel_ms(ctx):
@@ -642,8 +642,9 @@ class Operator:
         """Message of the last failed call on this operator ('' if none)."""
         return mfe_last_error(self.ctx)
 
-    def set_timing(self, enabled=True):
-        mfe_set_timing(self.ctx, enabled)
+    def set_timing(self, every=1):
+        """Record the apply kernel of every `every`-th apply (True/1: each, 0/False: off)."""
+        mfe_set_timing(self.ctx, int(every))
 
     def apply_kernel_ms(self):
         return mfe_apply_kernel_ms(self.ctx)

@@ -313,7 +313,8 @@ struct mfe_ctx {
     float* d_nbuf = nullptr;     // features, two hidden layers, output, scale
     double* d_fcg = nullptr;     // flexible CG directions and their images
     // timing of the apply kernel
-    bool timing = false;
+    int timing = 0;          // record every timing-th apply (0: none)
+    int64_t timing_seq = 0;  // applies since timing was set
     std::vector<hipEvent_t> ev_start, ev_stop;
     int ev_used = 0;
 };
@@ -934,7 +935,9 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         }
         MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
     }
-    const bool timed = c->timing;
+    // timed applies: the dispatch itself records the kernel's start and end
+    mfe::LaunchTiming tm;
+    const bool timed = c->timing > 0 && c->timing_seq++ % c->timing == 0;
     if (timed) {
         if (c->ev_used == (int)c->ev_start.size()) {
             hipEvent_t a, b;
@@ -943,13 +946,11 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
             c->ev_start.push_back(a);
             c->ev_stop.push_back(b);
         }
-        MFE_HIP(c, hipEventRecord(c->ev_start[c->ev_used], s));
+        tm.start = c->ev_start[c->ev_used];
+        tm.stop = c->ev_stop[c->ev_used];
     }
-    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep));
-    if (timed) {
-        MFE_HIP(c, hipEventRecord(c->ev_stop[c->ev_used], s));
-        c->ev_used++;
-    }
+    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep, tm));
+    if (timed) c->ev_used++;
     if (mask) {
         if (fp32)
             MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const float*>(w), p.v32, s));
@@ -2245,9 +2246,12 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
 
 extern "C" {
 
-int mfe_set_timing(mfe_ctx* c, int enabled) {
+int mfe_set_timing(mfe_ctx* c, int every) {
     if (!c) return MFE_EINVAL;
-    c->timing = enabled != 0;
+    c->err.clear();
+    if (every < 0) return fail(c, MFE_EINVAL, "timing interval must be >= 0");
+    c->timing = every;
+    c->timing_seq = 0;
     c->ev_used = 0;
     return MFE_OK;
 }

@@ -26,6 +26,8 @@
 
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "mfe_device.hpp"
 #include "mfe_kernels.hpp"
 
@@ -1184,37 +1186,38 @@ static MfmaMats<N> make_mfma_mats(const Tables1D& t) {
 }
 
 template <int N, int MODE, typename R, bool HX, int SW = 0>
-static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream,
-                            const MfmaMats<N>& MM = MfmaMats<N>{}) {
+static hipError_t launch_nm(const Tables<N>& T, const KParams& p, hipStream_t stream, const MfmaMats<N>& MM,
+                            const LaunchTiming& tm) {
     const int nb = p.nbx * p.nby * p.nbz;
-    if constexpr (std::is_same_v<R, float>) {
-        const Tables<N, float> TF = to_float<N>(T);
-        hipLaunchKernelGGL((cell_kernel<N, MODE, float, HX, SW>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, TF,
-                           MM);
-    } else {
-        hipLaunchKernelGGL((cell_kernel<N, MODE, double, HX>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, T,
-                           MM);
-    }
+    Tables<N, R> TR;
+    if constexpr (std::is_same_v<R, float>) TR = to_float<N>(T);
+    else TR = T;
+    if (tm.start)
+        hipExtLaunchKernelGGL((cell_kernel<N, MODE, R, HX, SW>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, tm.start,
+                              tm.stop, 0, p, T, TR, MM);
+    else
+        hipLaunchKernelGGL((cell_kernel<N, MODE, R, HX, SW>), dim3(nb), dim3(Geo<N, HX>::NT), 0, stream, p, T, TR, MM);
     return hipGetLastError();
 }
 
 // the apply modes with matrix-core sweeps of the w field (boxes)
 template <int N, int SW>
 static hipError_t launch_mfma_n(int mode, const Tables<N>& T, const MfmaMats<N>& MM, const KParams& p,
-                                hipStream_t s) {
+                                hipStream_t s, const LaunchTiming& tm) {
     switch (mode) {
-        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, false, SW>(T, p, s, MM);
-        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float, false, SW>(T, p, s, MM);
-        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float, false, SW>(T, p, s, MM);
-        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float, false, SW>(T, p, s, MM);
-        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float, false, SW>(T, p, s, MM);
-        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float, false, SW>(T, p, s, MM);
+        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, false, SW>(T, p, s, MM, tm);
+        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float, false, SW>(T, p, s, MM, tm);
+        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float, false, SW>(T, p, s, MM, tm);
+        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float, false, SW>(T, p, s, MM, tm);
+        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float, false, SW>(T, p, s, MM, tm);
+        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float, false, SW>(T, p, s, MM, tm);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int N, bool HX>
-static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s, int sweep = 0) {
+static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t s, int sweep = 0,
+                           const LaunchTiming& tm = LaunchTiming{}) {
     const Tables<N> T = make_tables<N>(t);
     if (sweep != 0) {  // matrix-core sweeps: FP32 vectors and caches, structured boxes
         if constexpr (HX) {
@@ -1222,41 +1225,41 @@ static hipError_t launch_n(int mode, bool fp32, const Tables1D& t, const KParams
         } else {
             if (!fp32) return hipErrorInvalidValue;
             const MfmaMats<N> MM = make_mfma_mats<N>(t);
-            if (sweep == 1) return launch_mfma_n<N, 1>(mode, T, MM, p, s);
-            if (sweep == 3) return launch_mfma_n<N, 3>(mode, T, MM, p, s);
+            if (sweep == 1) return launch_mfma_n<N, 1>(mode, T, MM, p, s, tm);
+            if (sweep == 3) return launch_mfma_n<N, 3>(mode, T, MM, p, s, tm);
             return hipErrorInvalidValue;
         }
     }
     if (fp32) {
         switch (mode) {
-            case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, HX>(T, p, s);
-            case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float, HX>(T, p, s);
-            case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float, HX>(T, p, s);
-            case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float, HX>(T, p, s);
-            case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float, HX>(T, p, s);
-            case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, float, HX>(T, p, s);
-            case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, float, HX>(T, p, s);
-            case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float, HX>(T, p, s);
-            case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, float, HX>(T, p, s);
+            case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, float, HX>(T, p, s, MfmaMats<N>{}, tm);
+            case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, float, HX>(T, p, s, MfmaMats<N>{}, tm);
             default: return hipErrorInvalidValue;
         }
     }
     switch (mode) {
-        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, double, HX>(T, p, s);
-        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, double, HX>(T, p, s);
-        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, double, HX>(T, p, s);
-        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, double, HX>(T, p, s);
-        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, double, HX>(T, p, s);
-        case MODE_RESIDUAL: return launch_nm<N, MODE_RESIDUAL, double, HX>(T, p, s);
-        case MODE_STATE: return launch_nm<N, MODE_STATE, double, HX>(T, p, s);
-        case MODE_BUILD_GEOM: return launch_nm<N, MODE_BUILD_GEOM, double, HX>(T, p, s);
-        case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, double, HX>(T, p, s);
-        case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, double, HX>(T, p, s);
-        case MODE_ENERGY: return launch_nm<N, MODE_ENERGY, double, HX>(T, p, s);
-        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, double, HX>(T, p, s);
-        case MODE_RESIDUAL_SPLIT: return launch_nm<N, MODE_RESIDUAL_SPLIT, double, HX>(T, p, s);
-        case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, double, HX>(T, p, s);
-        case MODE_ENERGY_SPLIT: return launch_nm<N, MODE_ENERGY_SPLIT, double, HX>(T, p, s);
+        case MODE_APPLY_OTF: return launch_nm<N, MODE_APPLY_OTF, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_APPLY_OTF_GEOM: return launch_nm<N, MODE_APPLY_OTF_GEOM, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_APPLY_T2: return launch_nm<N, MODE_APPLY_T2, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_APPLY_T4: return launch_nm<N, MODE_APPLY_T4, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_APPLY_OTF_AD: return launch_nm<N, MODE_APPLY_OTF_AD, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_RESIDUAL: return launch_nm<N, MODE_RESIDUAL, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_STATE: return launch_nm<N, MODE_STATE, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_BUILD_GEOM: return launch_nm<N, MODE_BUILD_GEOM, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_BUILD_T2: return launch_nm<N, MODE_BUILD_T2, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_BUILD_T4: return launch_nm<N, MODE_BUILD_T4, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_ENERGY: return launch_nm<N, MODE_ENERGY, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_APPLY_OTF_AD_SPLIT: return launch_nm<N, MODE_APPLY_OTF_AD_SPLIT, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_RESIDUAL_SPLIT: return launch_nm<N, MODE_RESIDUAL_SPLIT, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_BUILD_T4_SPLIT: return launch_nm<N, MODE_BUILD_T4_SPLIT, double, HX>(T, p, s, MfmaMats<N>{}, tm);
+        case MODE_ENERGY_SPLIT: return launch_nm<N, MODE_ENERGY_SPLIT, double, HX>(T, p, s, MfmaMats<N>{}, tm);
         default: return hipErrorInvalidValue;
     }
 }

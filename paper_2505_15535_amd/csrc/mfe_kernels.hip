@@ -60,16 +60,16 @@ hipError_t launch_dense_tangent(const Tables1D& t, const KParams& p, double* A, 
 }
 
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32,
-                              int sweep) {
+                              int sweep, const LaunchTiming& tm) {
     if (p.ne <= 0) return hipSuccess;
-    if (p.conn) return sweep ? hipErrorInvalidValue : launch_cell_kernel_hex(mode, t, p, stream, fp32);
+    if (p.conn) return sweep ? hipErrorInvalidValue : launch_cell_kernel_hex(mode, t, p, stream, fp32, tm);
     switch (t.n) {
-        case 2: return launch_n<2, false>(mode, fp32, t, p, stream, sweep);
-        case 3: return launch_n<3, false>(mode, fp32, t, p, stream, sweep);
-        case 4: return launch_n<4, false>(mode, fp32, t, p, stream, sweep);
-        case 5: return launch_n<5, false>(mode, fp32, t, p, stream, sweep);
-        case 6: return launch_n<6, false>(mode, fp32, t, p, stream, sweep);
-        case 7: return launch_n<7, false>(mode, fp32, t, p, stream, sweep);
+        case 2: return launch_n<2, false>(mode, fp32, t, p, stream, sweep, tm);
+        case 3: return launch_n<3, false>(mode, fp32, t, p, stream, sweep, tm);
+        case 4: return launch_n<4, false>(mode, fp32, t, p, stream, sweep, tm);
+        case 5: return launch_n<5, false>(mode, fp32, t, p, stream, sweep, tm);
+        case 6: return launch_n<6, false>(mode, fp32, t, p, stream, sweep, tm);
+        case 7: return launch_n<7, false>(mode, fp32, t, p, stream, sweep, tm);
         default: return hipErrorInvalidValue;
     }
 }

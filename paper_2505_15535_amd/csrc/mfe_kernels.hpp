@@ -86,11 +86,19 @@ void hex_group_shape(int n, int* cells, int* points_per_group);
 // and the sweeps of w are FP32; only the apply and T2/T4 build modes exist so.
 // sweep = 1 or 3: the FP32 apply modes with the w-field sweeps on the matrix
 // cores (one or three bf16 pieces per operand; structured boxes only).
+// Start and stop events of a timed launch, recorded by the kernel's dispatch
+// itself (no extra commands on the stream); both null for an untimed launch.
+struct LaunchTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream,
-                              bool fp32 = false, int sweep = 0);
+                              bool fp32 = false, int sweep = 0, const LaunchTiming& tm = LaunchTiming{});
 // The general-mesh instantiations (p.conn != null), reached through
 // launch_cell_kernel and launch_diagonal.
-hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32);
+hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32,
+                                  const LaunchTiming& tm);
 
 // Nodal basis values S and their derivatives Sd at the Gauss points.
 struct DiagTables {

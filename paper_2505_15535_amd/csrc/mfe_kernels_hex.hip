@@ -6,15 +6,16 @@
 
 namespace mfe {
 
-hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32) {
+hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32,
+                                  const LaunchTiming& tm) {
     if (p.ne <= 0) return hipSuccess;
     switch (t.n) {
-        case 2: return launch_n<2, true>(mode, fp32, t, p, stream);
-        case 3: return launch_n<3, true>(mode, fp32, t, p, stream);
-        case 4: return launch_n<4, true>(mode, fp32, t, p, stream);
-        case 5: return launch_n<5, true>(mode, fp32, t, p, stream);
-        case 6: return launch_n<6, true>(mode, fp32, t, p, stream);
-        case 7: return launch_n<7, true>(mode, fp32, t, p, stream);
+        case 2: return launch_n<2, true>(mode, fp32, t, p, stream, 0, tm);
+        case 3: return launch_n<3, true>(mode, fp32, t, p, stream, 0, tm);
+        case 4: return launch_n<4, true>(mode, fp32, t, p, stream, 0, tm);
+        case 5: return launch_n<5, true>(mode, fp32, t, p, stream, 0, tm);
+        case 6: return launch_n<6, true>(mode, fp32, t, p, stream, 0, tm);
+        case 7: return launch_n<7, true>(mode, fp32, t, p, stream, 0, tm);
         default: return hipErrorInvalidValue;
     }
 }

@@ -313,3 +313,36 @@ def test_mesh_limits_are_refused(torch_dev):
         assert e.value.code == mfe.MFE_EJACOBIAN
     finally:
         mfe.mfe_destroy(ctx)
+
+
+def test_timed_applies(torch_dev):
+    """Timed applies (start and stop events recorded by the dispatch) give the
+    same product and one positive duration per timed launch."""
+    torch, dev = torch_dev
+    cfg = synthetic.get_config("cube4_q2_jit")
+    verts = cfg.vertices()
+    op = _op(torch_dev, cfg.nx, cfg.ny, cfg.nz, cfg.degree, verts, cfg.mu, cfg.lam)
+    op.set_state(_to(torch_dev, cfg.displacement()))
+    w = _to(torch_dev, cfg.test_vector(0))
+    for s in ("t2", "otf"):
+        op.build_cache(s)
+        ref = op.apply(w, strategy=s).cpu().numpy()
+        op.set_timing(True)
+        outs = [op.apply(w, strategy=s).cpu().numpy() for _ in range(3)]
+        ms, n = op.apply_kernel_ms()
+        op.set_timing(False)
+        assert n == 3 and ms > 0.0, (s, ms, n)
+        for v in outs:
+            assert _rel(v, ref) <= 1e-14, s
+        op.apply(w, strategy=s)                 # untimed: nothing recorded
+        op.set_timing(True)
+        assert op.apply_kernel_ms()[1] == 0
+        op.set_timing(2)                        # every second apply, starting with the first
+        for _ in range(5):
+            op.apply(w, strategy=s)
+        assert op.apply_kernel_ms()[1] == 3
+        op.set_timing(False)
+    import paper_2505_15535_amd as mfe
+    with pytest.raises(mfe.MfeError) as e:
+        op.set_timing(-1)
+    assert e.value.code == mfe.MFE_EINVAL
