@@ -6,9 +6,12 @@ A step is one application v = K(u) w of the tangent on the 48^3 Q2 box
 (2,738,019 DoF), with the linearisation point and the per-point caches set up
 before the timed region (they are built once per linearisation point; their
 build time is reported separately).  Every strategy is timed; the headline
-`value` is the fastest one.  Beside it, under "mixed": FP64 and FP32-sweep
-applies on the Q4 24^3 and Q6 12^3 boxes (and the headline box) with the
-error of the FP32 result against the FP64 one; per strategy, "cold" times the apply with the caches flushed between applies;
+`value` is the fastest one; kernel durations (roofline) come from every
+10th launch of the timed steps.  Beside it, under "mixed": FP64 applies and
+applies with FP32 vectors and caches whose sweeps run in FP32 on the vector
+ALUs or on the matrix cores (bf16x3, bf16), on the Q4 24^3 and Q6 12^3 boxes
+(and the headline box), with the error of each against the FP64 result; per
+strategy, "cold" times the apply with the caches flushed between applies;
 "cpu_csr" is the assembled-matrix product on the host cores; under "hex": the apply on
 general hexahedral meshes (the headline box given as one, and an unstructured
 mesh of the same size); under "newton": the twisted beam (64x16x16 Q2,
