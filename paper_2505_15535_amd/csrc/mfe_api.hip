@@ -1965,6 +1965,45 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     if (bnorm == 0.0) return MFE_OK;
     if (flexible && gmg) return fcg(c, o, net, x, r, z, bnorm, s, iters, rel, net_fallbacks);
     double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    if (gmg) {
+        // The same iteration with alpha and beta formed on the device from
+        // device-resident dot products, so each iteration waits for the host
+        // once (for the stopping test) instead of three times.  S[0] = p.Ap,
+        // S[2] = r.r after the update, S[4] and S[6] = r.z of the current and
+        // the next iterate.  A non-positive r.z (preconditioner) or p.Ap
+        // (curvature) zeroes the next update on the device and is reported at
+        // the following wait, with x, r and the iteration count as the
+        // host-side loop leaves them.
+        double* S = out + 8;
+        c->h_scalars[8] = rz;
+        MFE_HIP(c, hipMemcpyAsync(S + 4, c->h_scalars + 8, sizeof(double), hipMemcpyHostToDevice, s));
+        int cur = 0;
+        for (int it = 1; it <= o->max_cg; ++it) {
+            rc = mfe_apply_tangent(c, pv, Ap, o->strategy, MFE_FP64, s);
+            if (rc != MFE_OK) return rc;
+            double* rzc = S + 4 + 2 * cur;
+            MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, c->d_partials, S, s));
+            MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, nullptr, rzc, S, n, c->d_partials, S + 2, s));
+            MFE_HIP(c, hipMemcpyAsync(c->h_scalars, S, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+            MFE_HIP(c, hipStreamSynchronize(s));
+            const double pAp = c->h_scalars[0], rzh = c->h_scalars[4 + 2 * cur];
+            if (!(rzh > 0.0)) return fail(c, MFE_ENOTCONV, "preconditioner is not positive definite");
+            if (!(pAp > 0.0)) {
+                if (it == 1 && pAp < 0.0) MFE_HIP(c, mfe::launch_axpby(rzh / -pAp, pv, 0.0, x, n, s));
+                return fail(c, MFE_ENOTCONV, "CG breakdown: p.Kp <= 0 (tangent not positive definite)");
+            }
+            iters = it;
+            rel = std::sqrt(c->h_scalars[2]) / bnorm;
+            if (rel <= o->cg_rtol) return MFE_OK;
+            rc = gmg_apply(c, o, r, z, s);
+            if (rc != MFE_OK) return rc;
+            double* rzn = S + 4 + 2 * (1 - cur);
+            MFE_HIP(c, mfe::launch_dot2(r, z, nullptr, nullptr, n, c->d_partials, rzn, s));
+            MFE_HIP(c, mfe::launch_p_update_dev(z, rzn, rzc, pv, n, s));
+            cur = 1 - cur;
+        }
+        return fail(c, MFE_ENOTCONV, "CG did not reach its tolerance");
+    }
     for (int it = 1; it <= o->max_cg; ++it) {
         rc = mfe_apply_tangent(c, pv, Ap, o->strategy, MFE_FP64, s);
         if (rc != MFE_OK) return rc;

@@ -139,6 +139,15 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, const 
 hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap, const double* dinv,
                             double alpha, int64_t n, double* partials, double* out, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+// launch_cg_update with alpha = rz[0] / pAp[0] read on the device (alpha = 0,
+// so x and r unchanged, unless both are positive)
+hipError_t launch_cg_update_dev(double* x, double* r, double* z, const double* p, const double* Ap,
+                                const double* dinv, const double* rz, const double* pAp, int64_t n, double* partials,
+                                double* out, hipStream_t s);
+// p = z + (rz_new[0] / rz_old[0]) p with the ratio formed on the device (0
+// unless rz_old[0] > 0)
+hipError_t launch_p_update_dev(const double* z, const double* rz_new, const double* rz_old, double* p, int64_t n,
+                               hipStream_t s);
 hipError_t launch_scale_mul(double scale, const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
 // d = 1/d (1/|d| with absolute); *bad = 1 where that is not positive and finite
 // Flexible CG with a window of kMaxDirs earlier directions: out[j] = z . Y[j]

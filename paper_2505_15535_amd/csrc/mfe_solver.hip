@@ -72,11 +72,10 @@ __global__ __launch_bounds__(kRedThreads) void sum_kernel(const double* __restri
 }
 
 // x += alpha p; r -= alpha Ap; z = dinv .* r (z = r without dinv); partial (r.r, r.z)
-__global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
-                                                                double* __restrict__ z, const double* __restrict__ p,
-                                                                const double* __restrict__ Ap,
-                                                                const double* __restrict__ dinv, double alpha,
-                                                                int64_t n, double* __restrict__ partials) {
+__device__ __forceinline__ void cg_update_body(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                               const double* __restrict__ p, const double* __restrict__ Ap,
+                                               const double* __restrict__ dinv, double alpha, int64_t n,
+                                               double* __restrict__ partials) {
     __shared__ double sh[kRedThreads / 64];
     double s0 = 0.0, s1 = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -95,6 +94,39 @@ __global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double* __restri
         partials[blockIdx.x] = t0;
         partials[gridDim.x + blockIdx.x] = t1;
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                                double* __restrict__ z, const double* __restrict__ p,
+                                                                const double* __restrict__ Ap,
+                                                                const double* __restrict__ dinv, double alpha,
+                                                                int64_t n, double* __restrict__ partials) {
+    cg_update_body(x, r, z, p, Ap, dinv, alpha, n, partials);
+}
+
+// The same with alpha = rz / pAp read from device memory, and alpha = 0
+// (nothing changes) unless both are positive.
+__global__ __launch_bounds__(kRedThreads) void cg_update_dev_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                                    double* __restrict__ z,
+                                                                    const double* __restrict__ p,
+                                                                    const double* __restrict__ Ap,
+                                                                    const double* __restrict__ dinv,
+                                                                    const double* __restrict__ rz,
+                                                                    const double* __restrict__ pAp, int64_t n,
+                                                                    double* __restrict__ partials) {
+    const double a = rz[0], b = pAp[0];
+    cg_update_body(x, r, z, p, Ap, dinv, (a > 0.0 && b > 0.0) ? a / b : 0.0, n, partials);
+}
+
+// p = z + beta p with beta = rz_new / rz_old read from device memory (0
+// unless rz_old > 0)
+__global__ void p_update_dev_kernel(const double* __restrict__ z, const double* __restrict__ rz_new,
+                                    const double* __restrict__ rz_old, double* __restrict__ p, int64_t n) {
+    const double o = rz_old[0];
+    const double beta = o > 0.0 ? rz_new[0] / o : 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = fma(1.0, z[i], beta * p[i]);
 }
 
 // y = a x + b y
@@ -179,6 +211,22 @@ hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, co
     hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kRedThreads), 0, s, x, r, z, p, Ap, dinv, alpha, n,
                        partials);
     hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_dev(double* x, double* r, double* z, const double* p, const double* Ap,
+                                const double* dinv, const double* rz, const double* pAp, int64_t n, double* partials,
+                                double* out, hipStream_t s) {
+    const unsigned nb = grid_for(n);
+    hipLaunchKernelGGL(cg_update_dev_kernel, dim3(nb), dim3(kRedThreads), 0, s, x, r, z, p, Ap, dinv, rz, pAp, n,
+                       partials);
+    hipLaunchKernelGGL(reduce2_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_p_update_dev(const double* z, const double* rz_new, const double* rz_old, double* p, int64_t n,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(p_update_dev_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, z, rz_new, rz_old, p, n);
     return hipGetLastError();
 }
 
