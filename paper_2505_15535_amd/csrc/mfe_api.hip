@@ -279,6 +279,8 @@ struct mfe_ctx {
     double* d_energy = nullptr;  // per-brick energy partials and their sum
     double* d_partials = nullptr;
     double* h_scalars = nullptr;
+    double* d_lz = nullptr;  // eigenvalue estimate: device history of its CG coefficients
+    double* h_lz = nullptr;  // and its pinned host copy
     int* d_bad = nullptr;
     // host copies used to derive coarser levels
     std::vector<double> h_verts;
@@ -536,6 +538,8 @@ void mfe_destroy(mfe_ctx* c) {
     dfree(c->d_partials);
     dfree(c->d_bad);
     if (c->h_scalars) (void)hipHostFree(c->h_scalars);
+    dfree(c->d_lz);
+    if (c->h_lz) (void)hipHostFree(c->h_lz);
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_stop) (void)hipEventDestroy(e);
     if (c->mg_stream) (void)hipStreamDestroy(c->mg_stream);
@@ -1394,44 +1398,64 @@ int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
     double* z = L.v64.tmp1;
     double* pv = L.v64.d;
     double* Ap = L.v64.r;
-    double* out = c->d_partials + 2 * mfe::kDotBlocks;
+    // The CG steps run with alpha and beta formed on the device; their dot
+    // products stay in a device history (hp + 2k: p.Ap of step k; hr + 2k:
+    // (r.r, r.z) before step k), which the host reads only once the stopping
+    // test can fire (after step 6, then after every step) and replays with
+    // the same arithmetic.  Steps past a stop only do discarded work.
+    constexpr int kHist = 2 * 17;
+    if (!c->d_lz) MFE_HIP(c, hipMalloc(&c->d_lz, 2 * kHist * sizeof(double)));
+    if (!c->h_lz) MFE_HIP(c, hipHostMalloc(&c->h_lz, 2 * kHist * sizeof(double), hipHostMallocDefault));
+    double* hp = c->d_lz;
+    double* hr = c->d_lz + kHist;
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, r, n, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, r, z, n, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
-    double rr, rz;
-    int rc = dotn(c, n, r, r, r, z, s, rr, rz);
-    if (rc != MFE_OK) return rc;
+    MFE_HIP(c, mfe::launch_dot2(r, r, r, z, n, c->d_partials, hr, s));
     std::vector<double> diag, off;
     double alpha_prev = 0.0, beta_prev = 0.0;
-    for (int k = 0; k < m; ++k) {
-        rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
+    const int first = std::min(5, m - 1);
+    int done = 0;
+    bool stop = false;
+    for (int k = 0; k < m && !stop; ++k) {
+        int rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
         if (rc != MFE_OK) return L.ctx != c ? child_fail(c, L.ctx, rc, "apply") : rc;
-        double pAp, unused;
-        rc = dotn(c, n, pv, Ap, nullptr, nullptr, s, pAp, unused);
-        if (rc != MFE_OK) return rc;
-        if (!(pAp > 0.0) || !std::isfinite(pAp))
-            return fail(c, MFE_ENOTCONV, "eigenvalue estimate: level tangent is not positive definite");
-        const double alpha = rz / pAp;
-        diag.push_back(1.0 / alpha + (k > 0 ? beta_prev / alpha_prev : 0.0));
-        MFE_HIP(c, mfe::launch_cg_update(x, r, z, pv, Ap, L.v64.dinv, alpha, n, c->d_partials, out, s));
-        MFE_HIP(c, hipMemcpyAsync(c->h_scalars, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, c->d_partials, hp + 2 * k, s));
+        MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, L.v64.dinv, hr + 2 * k + 1, hp + 2 * k, n, c->d_partials,
+                                             hr + 2 * (k + 1), s));
+        MFE_HIP(c, mfe::launch_p_update_dev(z, hr + 2 * (k + 1) + 1, hr + 2 * k + 1, pv, n, s));
+        if (k < first) continue;
+        MFE_HIP(c, hipMemcpyAsync(c->h_lz, c->d_lz, 2 * kHist * sizeof(double), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
-        const double rz_new = c->h_scalars[1];
-        if (!(rz_new > 1e-30 * rz)) break;  // invariant subspace found
-        const double beta = rz_new / rz;
-        if (k >= 5) {  // converged estimate?
-            std::vector<double> o2(off.begin(), off.end());
-            o2.resize(diag.size() - 1);
-            const double est = tridiag_lmax(diag, o2);
-            if (k > 5 && std::fabs(est - lmax) <= 0.005 * est) break;
-            lmax = est;
+        const double* Hp = c->h_lz;
+        const double* Hr = c->h_lz + kHist;
+        for (int j = done; j <= k && !stop; ++j) {
+            const double rz = Hr[2 * j + 1], pAp = Hp[2 * j], rz_new = Hr[2 * (j + 1) + 1];
+            if (!(pAp > 0.0) || !std::isfinite(pAp))
+                return fail(c, MFE_ENOTCONV, "eigenvalue estimate: level tangent is not positive definite");
+            const double alpha = rz / pAp;
+            diag.push_back(1.0 / alpha + (j > 0 ? beta_prev / alpha_prev : 0.0));
+            if (!(rz_new > 1e-30 * rz)) {  // invariant subspace found
+                stop = true;
+                break;
+            }
+            const double beta = rz_new / rz;
+            if (j >= 5) {  // converged estimate?
+                std::vector<double> o2(off.begin(), off.end());
+                o2.resize(diag.size() - 1);
+                const double est = tridiag_lmax(diag, o2);
+                if (j > 5 && std::fabs(est - lmax) <= 0.005 * est) {
+                    stop = true;
+                    break;
+                }
+                lmax = est;
+            }
+            if (j + 1 < m) off.push_back(std::sqrt(beta) / alpha);
+            alpha_prev = alpha;
+            beta_prev = beta;
         }
-        if (k + 1 < m) off.push_back(std::sqrt(beta) / alpha);
-        MFE_HIP(c, mfe::launch_axpby(1.0, z, beta, pv, n, s));
-        rz = rz_new;
-        alpha_prev = alpha;
-        beta_prev = beta;
+        done = k + 1;
     }
     off.resize(diag.size() > 0 ? diag.size() - 1 : 0);
     lmax = tridiag_lmax(diag, off);
