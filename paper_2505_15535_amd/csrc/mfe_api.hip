@@ -291,6 +291,11 @@ struct mfe_ctx {
     int mg_request = -1;  // mg_levels the hierarchy was built for
     // HIP graph of one preconditioner application
     hipStream_t mg_stream = nullptr;
+    // the coarsest level's direct-solve set-up runs on its own stream beside
+    // the other levels' eigenvalue estimates (default priority)
+    hipStream_t side_stream = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
+    int* d_bad_dense = nullptr;
     hipGraphExec_t mg_exec = nullptr;
     bool mg_graph_valid = false;
     const double* mg_graph_r = nullptr;
@@ -543,6 +548,10 @@ void mfe_destroy(mfe_ctx* c) {
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_stop) (void)hipEventDestroy(e);
     if (c->mg_stream) (void)hipStreamDestroy(c->mg_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->side_fork) (void)hipEventDestroy(c->side_fork);
+    if (c->side_join) (void)hipEventDestroy(c->side_join);
+    if (c->d_bad_dense) (void)hipFree(c->d_bad_dense);
     delete c;
 }
 
@@ -1470,8 +1479,11 @@ int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
 // second-order cache, which must be current.  ok = false when there are
 // more than kDenseMax free dofs or the tangent is not positive definite
 // (then the level is smoothed instead).
-int dense_setup(mfe_ctx* c, MGLevel& L, bool fp32, hipStream_t s, bool& ok) {
-    ok = false;
+// Launch half (on stream s): assembly and sweep inversion, the pivot check
+// into c->d_bad_dense; returns with launched = false when the level has no
+// or too many free dofs.  The finish half reads the check.
+int dense_launch(mfe_ctx* c, MGLevel& L, hipStream_t s, bool& launched) {
+    launched = false;
     mfe_ctx* lc = L.ctx;
     const int n = (int)lc->n_dofs;
     if (!L.dense) {  // the constraints of a level are fixed for the life of the hierarchy
@@ -1498,9 +1510,16 @@ int dense_setup(mfe_ctx* c, MGLevel& L, bool fp32, hipStream_t s, bool& ok) {
     KParams p = base_params(lc);
     p.cache = lc->d_cache[1];
     MFE_HIP(c, mfe::launch_dense_tangent(lc->tab, p, A, n, s));
-    MFE_HIP(c, mfe::launch_sweep_inverse(A, n, L.dense_free, nf, L.dense, c->d_bad, s));
+    if (!c->d_bad_dense) MFE_HIP(c, hipMalloc(&c->d_bad_dense, sizeof(int)));
+    MFE_HIP(c, mfe::launch_sweep_inverse(A, n, L.dense_free, nf, L.dense, c->d_bad_dense, s));
+    launched = true;
+    return MFE_OK;
+}
+
+int dense_finish(mfe_ctx* c, MGLevel& L, bool fp32, hipStream_t s, bool& ok) {
+    const size_t nf2 = (size_t)L.dense_nf * L.dense_nf;
     int bad = 1;
-    MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad_dense, sizeof(int), hipMemcpyDeviceToHost, s));
     MFE_HIP(c, hipStreamSynchronize(s));
     ok = bad == 0;
     if (ok && fp32) {
@@ -1550,18 +1569,49 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
         MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
         if (bad) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
-        L.dense_ok = false;
-        const int64_t n_free = lc->n_dofs - lc->n_con;
-        if (o->coarse_direct && l + 1 == c->mg.size() && lc->n_dofs <= 1024 && n_free > 0 &&
-            n_free <= mfe::kDenseMax) {
-            rc = dense_setup(c, L, fp32, s, L.dense_ok);
+    }
+    // The coarsest level's direct-solve set-up (one workgroup, ~0.6 ms) runs
+    // on the side stream while the other levels' eigenvalue estimates run on
+    // s; a failed pivot check falls back to smoothing that level.
+    const size_t nl = c->mg.size();
+    MGLevel& Lc = c->mg[nl - 1];
+    for (MGLevel& L : c->mg) L.dense_ok = false;
+    bool dense = false;
+    // an early return leaves no side-stream work behind
+    struct SideGuard {
+        hipStream_t side = nullptr;
+        ~SideGuard() {
+            if (side) (void)hipStreamSynchronize(side);
+        }
+    } guard;
+    {
+        const int64_t n_free = Lc.ctx->n_dofs - Lc.ctx->n_con;
+        if (o->coarse_direct && Lc.ctx->n_dofs <= 1024 && n_free > 0 && n_free <= mfe::kDenseMax) {
+            if (!c->side_stream) MFE_HIP(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+            if (!c->side_fork) MFE_HIP(c, hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming));
+            if (!c->side_join) MFE_HIP(c, hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming));
+            MFE_HIP(c, hipEventRecord(c->side_fork, s));
+            MFE_HIP(c, hipStreamWaitEvent(c->side_stream, c->side_fork, 0));
+            guard.side = c->side_stream;
+            const int rc = dense_launch(c, Lc, c->side_stream, dense);
             if (rc != MFE_OK) return rc;
+            MFE_HIP(c, hipEventRecord(c->side_join, c->side_stream));
+        }
+    }
+    for (size_t l = 0; l < nl; ++l) {
+        MGLevel& L = c->mg[l];
+        mfe_ctx* lc = L.ctx;
+        if (l + 1 == nl && dense) {
+            MFE_HIP(c, hipStreamWaitEvent(s, c->side_join, 0));
+            const int rc = dense_finish(c, L, fp32, s, L.dense_ok);
+            if (rc != MFE_OK) return rc;
+            guard.side = nullptr;  // joined: dense_finish waited for it
         }
         if (L.dense_ok) {
             L.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
         } else {
             double lam = 0.0;
-            rc = lanczos_lmax(c, L, s, lam);
+            const int rc = lanczos_lmax(c, L, s, lam);
             if (rc != MFE_OK) return rc;
             L.lmax = lam;
         }
