@@ -66,7 +66,7 @@ typedef enum mfe_status {
  *                 M = J_g^-1 F^-1 (9), tau*JxW (6) and two scalars (17 doubles).
  *   MFE_T4        cached fourth-order spatial tangent J c * JxW (21, Voigt),
  *                 tau*JxW (6) and M (9): 36 doubles (Alg. 2; storage count of
- *                 Sec. 3.2.3).
+ *                 Sec. 3.2.2).
  *   MFE_OTF_AD    on the fly like MFE_OTF, but G is obtained as the
  *                 directional derivative of P along the seed dF = Grad w by
  *                 forward-mode dual numbers (Sec. 2.5.1, eq. LG).            */
@@ -383,6 +383,20 @@ int mfe_axpby(mfe_ctx* ctx, double a, const double* x_dev, double b, double* y_d
  * constrained dofs), from the second-order cache, which this call builds if
  * it is stale.  d_dev: device array of n_dofs doubles.  Asynchronous. */
 int mfe_diagonal(mfe_ctx* ctx, double* d_dev, void* stream);
+
+/* Summation order of mfe_apply_tangent (Alg. 1/Alg. 2 "scatter"): on = 0
+ * (default), every brick of cells adds the nodes it shares with a
+ * neighbouring brick with atomics, so the order of the additions at such a
+ * node (and the last bits of v) can change from call to call; on != 0, the
+ * bricks run as eight launches in a fixed order, one per parity class of the
+ * brick position (bx & 1, by & 1, bz & 1), whose bricks share no node, and
+ * shared nodes are added with plain read-add-writes: v is bitwise
+ * reproducible.  Within a brick the cells' contributions are summed in a
+ * fixed order in either mode.  The coloured mode is built for Q2 structured
+ * boxes with the vector-ALU sweeps (MFE_FP64, MFE_SF_FP32); other meshes,
+ * degrees and precisions then return MFE_EUNSUPPORTED from the apply.
+ * Timing (below) covers the first to the last of the eight launches. */
+int mfe_set_deterministic(mfe_ctx* ctx, int on);
 
 /* Kernel timing of mfe_apply_tangent.  mfe_set_timing(ctx, every) records
  * the apply kernel of every `every`-th call from now on (1: every call, 0:

@@ -94,6 +94,7 @@ _SIGS = {
     "mfe_residual": (_i, [_vp, _vp, _vp, _vp]),
     "mfe_energy": (_i, [_vp, _vp, ctypes.POINTER(_d), _vp]),
     "mfe_set_timing": (_i, [_vp, _i]),
+    "mfe_set_deterministic": (_i, [_vp, _i]),
     "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
     "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
     "mfe_diagonal": (_i, [_vp, _vp, _vp]),
@@ -331,6 +332,10 @@ def mfe_diagonal(ctx, d_dev_ptr, stream=None):
 
 def mfe_set_timing(ctx, every):
     return _check(ctx, _lib.mfe_set_timing(ctx, int(every)))
+
+
+def mfe_set_deterministic(ctx, on):
+    return _check(ctx, _lib.mfe_set_deterministic(ctx, int(bool(on))))
 
 
 def mfe_apply_kernel_ms(ctx):
@@ -645,6 +650,10 @@ class Operator:
     def set_timing(self, every=1):
         """Record the apply kernel of every `every`-th apply (True/1: each, 0/False: off)."""
         mfe_set_timing(self.ctx, int(every))
+
+    def set_deterministic(self, on=True):
+        """Coloured, bitwise reproducible summation of the applies (Q2 boxes)."""
+        mfe_set_deterministic(self.ctx, on)
 
     def apply_kernel_ms(self):
         return mfe_apply_kernel_ms(self.ctx)

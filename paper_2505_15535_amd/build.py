@@ -11,7 +11,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmfe.so")
-SOURCES = ["mfe_kernels.hip", "mfe_kernels_hex.hip", "mfe_mesh.hip", "mfe_solver.hip", "mfe_mg.hip",
+SOURCES = ["mfe_kernels.hip", "mfe_kernels_wave.hip", "mfe_kernels_hex.hip", "mfe_mesh.hip", "mfe_solver.hip", "mfe_mg.hip",
            "mfe_net.hip", "mfe_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

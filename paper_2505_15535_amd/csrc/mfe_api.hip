@@ -260,7 +260,10 @@ struct mfe_ctx {
     // constraints
     double* d_wmask = nullptr;   // w with constrained entries zeroed
     int64_t* d_cidx = nullptr;
+    uint32_t* d_cmask = nullptr; // constrained dofs as a bitmap (bit d % 32 of word d / 32)
     int64_t n_con = 0;
+    // tangent applies in the coloured, bitwise reproducible mode
+    bool deterministic = false;
     // state and caches
     double* d_u = nullptr;
     bool has_state = false;
@@ -324,6 +327,7 @@ struct mfe_ctx {
     int64_t timing_seq = 0;  // applies since timing was set
     std::vector<hipEvent_t> ev_start, ev_stop;
     int ev_used = 0;
+    hipEvent_t ev_scratch = nullptr;  // unused end of a timed coloured launch
 };
 
 namespace {
@@ -400,6 +404,7 @@ void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_cellmat);
     dfree(c->d_wmask);
     dfree(c->d_cidx);
+    dfree(c->d_cmask);
     dfree(c->d_u);
     for (int i = 0; i < kNumCaches; ++i) {
         dfree(c->d_cache[i]);
@@ -547,6 +552,7 @@ void mfe_destroy(mfe_ctx* c) {
     if (c->h_lz) (void)hipHostFree(c->h_lz);
     for (auto e : c->ev_start) (void)hipEventDestroy(e);
     for (auto e : c->ev_stop) (void)hipEventDestroy(e);
+    if (c->ev_scratch) (void)hipEventDestroy(c->ev_scratch);
     if (c->mg_stream) (void)hipStreamDestroy(c->mg_stream);
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     if (c->side_fork) (void)hipEventDestroy(c->side_fork);
@@ -794,10 +800,15 @@ int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
     MFE_HIP(c, hipDeviceSynchronize());
     dfree(c->d_cidx);
     dfree(c->d_wmask);
+    dfree(c->d_cmask);
     if (!idx.empty()) {
         MFE_HIP(c, hipMalloc(&c->d_wmask, c->n_dofs * sizeof(double)));
         MFE_HIP(c, hipMalloc(&c->d_cidx, idx.size() * sizeof(int64_t)));
         MFE_HIP(c, hipMemcpy(c->d_cidx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        std::vector<uint32_t> bits((c->n_dofs + 31) / 32, 0u);
+        for (int64_t d : idx) bits[d >> 5] |= 1u << (d & 31);
+        MFE_HIP(c, hipMalloc(&c->d_cmask, bits.size() * sizeof(uint32_t)));
+        MFE_HIP(c, hipMemcpy(c->d_cmask, bits.data(), bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     c->n_con = (int64_t)idx.size();
     c->h_cidx = idx;
@@ -928,10 +939,17 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
         p.cache32 = c->d_cache32[slot];
     }
     const bool mask = constrained && c->n_con > 0;
+    // the Q2 box kernel reads the constraint bitmap and writes v = w at the
+    // constrained dofs itself; the others read a masked copy of w and get the
+    // constrained entries of v copied afterwards
+    // (the coloured mode always runs it)
+    const bool wave = mfe::wave_apply(c->tab.n, mode, c->hex, sweep, fp32 || c->deterministic);
+    if (c->deterministic && !wave)
+        return fail(c, MFE_EUNSUPPORTED, "the coloured apply is built for Q2 structured boxes with vector-ALU sweeps");
     if (fp32) {
         p.w32 = static_cast<const float*>(w);
         p.v32 = static_cast<float*>(v);
-        if (mask) {  // the kernel reads w with the constrained entries zeroed
+        if (mask && !wave) {  // the kernel reads w with the constrained entries zeroed
             float* wm = reinterpret_cast<float*>(c->d_wmask);
             MFE_HIP(c, hipMemcpyAsync(wm, w, c->n_dofs * sizeof(float), hipMemcpyDeviceToDevice, s));
             MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0f, wm, s));
@@ -941,14 +959,16 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     } else {
         p.w = static_cast<const double*>(w);
         p.v = static_cast<double*>(v);
-        if (mask) {
+        if (mask && !wave) {
             MFE_HIP(c, hipMemcpyAsync(c->d_wmask, w, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
             MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, c->d_wmask, s));
             p.w = c->d_wmask;
         }
         MFE_HIP(c, mfe::launch_fill(p.v, c->n_dofs, 0.0, s));
     }
+    if (mask && wave) p.cmask = c->d_cmask;
     // timed applies: the dispatch itself records the kernel's start and end
+    // (in the coloured mode the first and the last of the eight launches)
     mfe::LaunchTiming tm;
     const bool timed = c->timing > 0 && c->timing_seq++ % c->timing == 0;
     if (timed) {
@@ -959,12 +979,33 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
             c->ev_start.push_back(a);
             c->ev_stop.push_back(b);
         }
+        if (c->deterministic && !c->ev_scratch) MFE_HIP(c, hipEventCreate(&c->ev_scratch));
         tm.start = c->ev_start[c->ev_used];
         tm.stop = c->ev_stop[c->ev_used];
     }
-    MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep, tm));
+    if (c->deterministic) {
+        // the eight parity classes of bricks in a fixed order; bricks of one
+        // class share no node, so each launch adds with plain read-add-writes
+        int first = 0, last = 0;
+        for (int col = 1; col <= 8; ++col)
+            if (mfe::colour_bricks(c->nbx, c->nby, c->nbz, col) > 0) {
+                if (!first) first = col;
+                last = col;
+            }
+        for (int col = 1; col <= 8; ++col) {
+            if (mfe::colour_bricks(c->nbx, c->nby, c->nbz, col) == 0) continue;
+            p.colour = col;
+            mfe::LaunchTiming tc;
+            if (timed && first == last) tc = tm;
+            else if (timed && col == first) tc.start = tm.start, tc.stop = c->ev_scratch;
+            else if (timed && col == last) tc.start = c->ev_scratch, tc.stop = tm.stop;
+            MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep, tc));
+        }
+    } else {
+        MFE_HIP(c, mfe::launch_cell_kernel(mode, c->tab, p, s, fp32, sweep, tm));
+    }
     if (timed) c->ev_used++;
-    if (mask) {
+    if (mask && !wave) {
         if (fp32)
             MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, static_cast<const float*>(w), p.v32, s));
         else
@@ -2358,6 +2399,13 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
 }  // extern "C"
 
 extern "C" {
+
+int mfe_set_deterministic(mfe_ctx* c, int on) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    c->deterministic = on != 0;
+    return MFE_OK;
+}
 
 int mfe_set_timing(mfe_ctx* c, int every) {
     if (!c) return MFE_EINVAL;

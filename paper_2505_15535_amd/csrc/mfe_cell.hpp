@@ -36,10 +36,10 @@ namespace mfe {
 // Bricks: a workgroup owns BX x BY x BZ neighbouring cells of the box.  The
 // Q2 shape can be chosen at build time (cells per direction).
 #ifndef MFE_Q2_BRICK_X
-#define MFE_Q2_BRICK_X 3
+#define MFE_Q2_BRICK_X 4
 #endif
 #ifndef MFE_Q2_BRICK_Y
-#define MFE_Q2_BRICK_Y 3
+#define MFE_Q2_BRICK_Y 2
 #endif
 #ifndef MFE_Q2_BRICK_Z
 #define MFE_Q2_BRICK_Z 1
@@ -101,6 +101,12 @@ __device__ __forceinline__ BrickPos brick_pos(const KParams& p) {
     using G = Geo<N, HX>;
     BrickPos b;
     b.brick = xcd_remap(blockIdx.x, gridDim.x);
+    if (!HX && p.colour > 0) {  // the launch holds only the bricks of one parity class
+        const int c = p.colour - 1, ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+        const int mx = (p.nbx - ox + 1) / 2, my = (p.nby - oy + 1) / 2;
+        const int i = b.brick % mx, r = b.brick / mx;
+        b.brick = (2 * i + ox) + p.nbx * ((2 * (r % my) + oy) + p.nby * (2 * (r / my) + oz));
+    }
     if constexpr (HX) {
         b.ex0 = b.brick * G::CPB;
         b.ey0 = b.ez0 = 0;

@@ -59,6 +59,12 @@ struct KParams {
     const unsigned short* lidx;
     double mu, lam;            // uniform material
     int* flag;                 // STATE: set to 1 if det F <= 0 somewhere
+    // Q2 box applies: constrained dofs as a bitmap (bit d % 32 of word d / 32),
+    // or null; colour 0 runs every brick with atomics on shared faces, colour
+    // 1..8 only the bricks of parity class colour - 1 (bx & 1 | (by & 1) << 1 |
+    // (bz & 1) << 2) with plain read-add-writes
+    const uint32_t* cmask;
+    int colour;
 };
 
 // 1D data of degree p = N-1 computed on the host: S (Lagrange basis on
@@ -95,6 +101,18 @@ struct LaunchTiming {
 
 hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hipStream_t stream,
                               bool fp32 = false, int sweep = 0, const LaunchTiming& tm = LaunchTiming{});
+// True when launch_cell_kernel runs a tangent apply of this kind with the
+// wavefront-per-two-cells kernel (Q2 structured boxes, vector-ALU sweeps),
+// which reads the constraint bitmap and the colour of KParams itself; fp32:
+// FP32 sweeps.  Launches with a colour (the coloured mode, which only that
+// kernel has) run it whenever wave_apply(..., fp32 = true) holds.
+bool wave_apply(int n, int mode, bool hex, int sweep, bool fp32);
+// The launch of those applies (reached through launch_cell_kernel).
+hipError_t launch_wave(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t stream,
+                       const LaunchTiming& tm);
+// Number of bricks of parity class `colour` - 1 (1..8) of a box of
+// nbx x nby x nbz bricks.
+int64_t colour_bricks(int nbx, int nby, int nbz, int colour);
 // The general-mesh instantiations (p.conn != null), reached through
 // launch_cell_kernel and launch_diagonal.
 hipError_t launch_cell_kernel_hex(int mode, const Tables1D& t, const KParams& p, hipStream_t stream, bool fp32,
