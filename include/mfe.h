@@ -239,6 +239,18 @@ int64_t mfe_cache_bytes(const mfe_ctx* ctx, int strategy);
 int mfe_apply_tangent(mfe_ctx* ctx, const void* w_dev, void* v_dev,
                       int strategy, int precision, void* stream);
 
+/* Allocation-free variant of mfe_energy, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): *energy_dev (a device double) = the stored energy at the
+ * displacement u_dev (device array of n_dofs doubles), written on `stream`;
+ * asynchronous, no host synchronisation.  The per-brick partial sums go to a
+ * fixed device array of 2^18 doubles (2 MiB) that each GPU holds for the
+ * life of the process; a mesh with more bricks of cells (workgroups) than
+ * that returns MFE_EINVAL.  Calls no hipMalloc/hipFree.  Calls on one GPU
+ * share the array: calls that overlap in time (other streams, other threads,
+ * other contexts on that GPU) race and must be serialised by the caller. */
+int mfe_energy_noalloc(mfe_ctx* ctx, const double* u_dev, double* energy_dev, void* stream);
+
 /* r = residual of the weak form at displacement u (eq. F without traction):
  * r_(a,i) = sum_cells sum_q JxW_q P_iA(F_q) Grad_A N_a, zero at constrained
  * dofs.  u_dev, r_dev: device arrays of n_dofs doubles, must not overlap.

@@ -93,6 +93,7 @@ _SIGS = {
     "mfe_apply_tangent": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "mfe_residual": (_i, [_vp, _vp, _vp, _vp]),
     "mfe_energy": (_i, [_vp, _vp, ctypes.POINTER(_d), _vp]),
+    "mfe_energy_noalloc": (_i, [_vp, _vp, _vp, _vp]),
     "mfe_set_timing": (_i, [_vp, _i]),
     "mfe_set_deterministic": (_i, [_vp, _i]),
     "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
@@ -215,6 +216,10 @@ def mfe_energy(ctx, u_dev_ptr, stream=None) -> float:
     e = _d()
     _check(ctx, _lib.mfe_energy(ctx, u_dev_ptr, ctypes.byref(e), stream))
     return e.value
+
+
+def mfe_energy_noalloc(ctx, u_dev_ptr, energy_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_energy_noalloc(ctx, u_dev_ptr, energy_dev_ptr, stream))
 
 
 def mfe_build_cache_fp32(ctx, strategy, stream=None):

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -169,6 +170,32 @@ void make_tables(int degree, Tables1D& t) {
         }
 }
 
+// Partial sums of the allocation-free energy (mfe_energy_noalloc): one double
+// per brick of cells.  Each GPU the library runs on holds its own copy for
+// the life of the process.
+constexpr int64_t kNoAllocDoubles = (int64_t)1 << 18;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Device address of `scratch` on the current device (the array's name in host
+// code is a stand-in, not that address), looked up once per device.
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+hipError_t scratch_address(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -328,6 +355,7 @@ struct mfe_ctx {
     std::vector<hipEvent_t> ev_start, ev_stop;
     int ev_used = 0;
     hipEvent_t ev_scratch = nullptr;  // unused end of a timed coloured launch
+    double* d_scratch = nullptr;      // this device's `scratch` array (not owned)
 };
 
 namespace {
@@ -530,6 +558,11 @@ int mfe_create(mfe_ctx** out, int hip_device) {
     c->device = hip_device;
     DeviceGuard g(hip_device);
     if (!g.ok || hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
+        delete c;
+        return MFE_EHIP;
+    }
+    if (scratch_address(hip_device, &c->d_scratch) != hipSuccess) {
+        (void)hipFree(c->d_flag);
         delete c;
         return MFE_EHIP;
     }
@@ -1037,6 +1070,27 @@ int mfe_energy(mfe_ctx* c, const double* u, double* energy, void* stream) {
     MFE_HIP(c, hipMemcpyAsync(c->h_scalars + 3, c->d_energy + nb, sizeof(double), hipMemcpyDeviceToHost, s));
     MFE_HIP(c, hipStreamSynchronize(s));
     *energy = c->h_scalars[3];
+    return MFE_OK;
+}
+
+int mfe_energy_noalloc(mfe_ctx* c, const double* u, double* energy, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!u || !energy) return fail(c, MFE_EINVAL, "null pointer");
+    const int64_t nb = (int64_t)c->nbx * c->nby * c->nbz;
+    if (nb > kNoAllocDoubles)
+        return fail(c, MFE_EINVAL, "mesh has " + std::to_string(nb) + " bricks of cells; the allocation-free energy "
+                                   "holds at most " + std::to_string(kNoAllocDoubles) + " partial sums");
+    if (overlaps(u, energy, c->n_dofs * (int64_t)sizeof(double))) return fail(c, MFE_EINVAL, "u and energy overlap");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams p = base_params(c);
+    p.u = u;
+    p.v = c->d_scratch;  // every partial is written before the sum reads it
+    MFE_HIP(c, mfe::launch_cell_kernel(c->model == MFE_MODEL_SPLIT ? mfe::MODE_ENERGY_SPLIT : mfe::MODE_ENERGY,
+                                       c->tab, p, s));
+    MFE_HIP(c, mfe::launch_sum(c->d_scratch, nb, energy, s));
     return MFE_OK;
 }
 
