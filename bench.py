@@ -144,30 +144,40 @@ def cpu_baseline(cfg, target_s: float = 12.0) -> dict:
     return {"value": rate, "unit": "GDoF/s", "cores": max(1, int(round(t_cpu / t_wall))), "kind": "oracle",
             "sample": f"naive FP64 cell loop (explicit 81-entry tangent, numpy) over {len(cells)} of "
                       f"{mesh.n_elems} cells of {cfg.name} in {t_wall:.1f} s, scaled by the cell fraction",
-            "host_threads": os.cpu_count()}
+            "host_threads": os.cpu_count(), "host": host_cpu()}
 
 
-def cpu_csr_baseline(nx: int = 10) -> dict:
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model, n = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                if line.startswith("processor"):
+                    n += 1
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": n}
+
+
+def cpu_csr_baseline(cfg) -> dict:
     """The assembled-matrix alternative the paper compares against (Sec.
-    3.2.2): the oracle's tangent assembled into CSR on a bounded box of the
-    headline workload's kind (nx^3 jittered Q2 cells, same material and
-    displacement recipe), then y = K w with the oracle's OpenMP CSR kernel on
-    all host cores, median of 10 products, reported as DoF/s.  The CSR
-    product's cost per DoF does not depend on the box size once the matrix
-    is larger than the host caches (here about 60 MB: a lower bound on the
-    per-DoF cost where the host cache holds the whole matrix)."""
+    3.2.2) at the headline workload's full size: the oracle's tangent of the
+    same box, state and material assembled into CSR by the oracle's C/OpenMP
+    assembly (same definition as the numpy assembly, pinned against it entry
+    by entry), then y = K w with the oracle's OpenMP CSR kernel on all host
+    cores, median of 10 products, reported as DoF/s."""
     import ctypes
 
     import numpy as np
-    from oracle.fem import Problem
+    from oracle.assemble_c import assemble_tangent_box
     from oracle.mesh import BoxMesh
-    import synthetic
 
-    cfg = synthetic.get_config("box48_q2")
-    verts = synthetic.box_vertices(nx, nx, nx, (1.0, 1.0, 1.0), 0.1, np.random.default_rng(7))
-    u = synthetic.sine_displacement(nx, nx, nx, 2, cfg.amplitude, np.random.default_rng(8))
+    mesh = BoxMesh(cfg.nx, cfg.ny, cfg.nz, cfg.degree, cfg.vertices())
     t0 = time.perf_counter()
-    K = Problem(BoxMesh(nx, nx, nx, 2, verts), cfg.mu, cfg.lam, chunk=256).assemble_tangent(u).tocsr()
+    indptr, indices, data, asm_threads = assemble_tangent_box(mesh, cfg.mu, cfg.lam, cfg.displacement())
     t_asm = time.perf_counter() - t0
     lib_path = os.path.join(ROOT, "oracle", "libcsr_spmv.so")
     if not os.path.exists(lib_path):
@@ -175,24 +185,24 @@ def cpu_csr_baseline(nx: int = 10) -> dict:
     lib = ctypes.CDLL(lib_path)
     lib.csr_spmv.restype = ctypes.c_int
     lib.csr_spmv.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5
-    indptr = np.ascontiguousarray(K.indptr, dtype=np.int64)
-    indices = np.ascontiguousarray(K.indices, dtype=np.int32)
-    data = np.ascontiguousarray(K.data, dtype=np.float64)
-    x = np.random.default_rng(9).standard_normal(K.shape[0])
+    n = indptr.size - 1
+    x = cfg.test_vector(0)
     y = np.empty_like(x)
     times, threads = [], 1
     for _ in range(11):
         t0 = time.perf_counter()
-        threads = lib.csr_spmv(K.shape[0], indptr.ctypes.data, indices.ctypes.data, data.ctypes.data,
-                               x.ctypes.data, y.ctypes.data)
+        threads = lib.csr_spmv(n, indptr.ctypes.data, indices.ctypes.data, data.ctypes.data, x.ctypes.data,
+                               y.ctypes.data)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times[1:]))
-    n = K.shape[0]
+    nnz = int(indptr[-1])
+    mb = (data.nbytes + indices.nbytes + indptr.nbytes) / 1e6
+    del indptr, indices, data
     return {"value": n / t / 1e9, "unit": "GDoF/s", "cores": int(threads), "kind": "oracle assembled CSR",
-            "sample": f"{nx}^3 jittered Q2 box, {n} DoF, {K.nnz} stored entries ({K.nnz / n:.0f} per row, "
-                      f"{(K.nnz * 12 + 8 * n) / 1e6:.0f} MB CSR); median of 10 OpenMP products; assembly "
-                      f"{t_asm:.1f} s (numpy, one core)",
-            "assembly_s": round(t_asm, 2), "spmv_ms": round(t * 1e3, 3)}
+            "sample": f"{cfg.description}: {n} DoF, {nnz} stored entries ({nnz / n:.1f} per row, {mb:.0f} MB CSR); "
+                      f"median of 10 OpenMP products",
+            "assembly_s": round(t_asm, 2), "assembly_threads": int(asm_threads), "spmv_ms": round(t * 1e3, 3),
+            "host": host_cpu()}
 
 
 # --------------------------------------------------------------------------- mixed precision
@@ -212,11 +222,12 @@ def time_applies(op, w, v, strategy, precision, steps, warmup):
     return step_ms, kern_ms
 
 
-def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
+def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4"), precisions=("fp64", "fp32")) -> dict:
     """FP64 applies and applies with FP32 vectors and caches whose sweeps run in
-    FP32 on the vector ALUs, or on the matrix cores as bf16x3 (three-piece
-    split, FP32-accurate) or bf16 (one product); error of each result against
-    the FP64 one (the FP64 path itself matches the oracle to 1e-12)."""
+    FP32 on the vector ALUs (and, with --mfma, on the matrix cores as bf16x3,
+    the three-piece split that is FP32-accurate, or bf16, one product); error
+    of each result against the FP64 one (the FP64 path itself matches the
+    oracle to 1e-12)."""
     import numpy as np
     import torch
 
@@ -234,7 +245,7 @@ def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
     out = {"n_dofs": op.n_dofs, "degree": cfg.degree, "description": cfg.description}
     for s in strategies:
         rec = {}
-        for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        for prec in precisions:
             w, elem = (w64, 8) if prec == "fp64" else (w32, 4)
             v = v64 if prec == "fp64" else torch.empty_like(w32)
             op.build_cache(s, precision=prec)
@@ -250,7 +261,7 @@ def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
         out[s] = rec
         print(f"[bench] mixed {name} {s}: " + ", ".join(
             f"{p} {rec[p]['gdofs']:.2f} GDoF/s" + (f" (err {rec[p]['rel_err_vs_fp64']:.1e})" if p != "fp64" else "")
-            for p in ("fp64", "fp32", "bf16x3", "bf16")), file=sys.stderr, flush=True)
+            for p in precisions), file=sys.stderr, flush=True)
     op.close()
     return out
 
@@ -355,15 +366,17 @@ def hex_leg(name, steps, warmup, strategies=("otf", "t2", "t4")) -> dict:
 
 
 # --------------------------------------------------------------------------- Newton-CG
-NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=8, max_cg=2000, newton_atol=1e-8,
+NEWTON_OPTS = dict(strategy="t2", preconditioner="gmg", max_newton=30, max_cg=2000, newton_atol=1e-8,
                    cg_rtol=1e-3, cheb_degree=4, cheb_range=15.0, coarse_degree=15, coarse_range=200.0,
-                   coarse_direct=1)
+                   coarse_direct=1, forcing=0.5)
 
 
 def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
     """Twisted beam: left face clamped, right face rotated by `degrees` about
-    the beam axis in `steps` load steps; time to ||R|| <= 1e-8 at the end of
-    the path with the FP64 V-cycle and with the FP32 V-cycle."""
+    the beam axis in `steps` equal load steps, each started from the last
+    converged state; inexact Newton (Eisenstat-Walker forcing, at most 0.5)
+    with GMG-preconditioned CG; time to ||R|| <= 1e-8 at the end of the path
+    with the FP64 V-cycle and with the FP32 V-cycle."""
     import numpy as np
     import torch
 
@@ -383,7 +396,7 @@ def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = op.solve_load_path(u, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, np.deg2rad(degrees) * t),
-                                  steps, mg_precision=prec, **NEWTON_OPTS)
+                                  steps, mg_precision=prec, extrapolate=False, **NEWTON_OPTS)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         res = float(np.linalg.norm(op.residual(u).cpu().numpy()))
@@ -392,7 +405,10 @@ def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
                      "load_steps_rejected": sum(1 for r in reps if r.get("failed")),
                      "newton_iterations": sum(r["newton_iterations"] for r in reps),
                      "cg_iterations": sum(r["cg_iterations"] for r in reps),
-                     "pc_fallbacks": sum(r.get("pc_fallbacks", 0) for r in reps)}
+                     "pc_fallbacks": sum(r.get("pc_fallbacks", 0) for r in reps),
+                     "per_step": [{"t": round(r["t"], 4), "newton": r["newton_iterations"], "cg": r["cg_iterations"],
+                                   "backtracks": r.get("backtracks", 0), "failed": bool(r.get("failed"))}
+                                  for r in reps]}
         out["n_dofs"] = op.n_dofs
         print(f"[bench] newton {prec} V-cycle: {secs:.2f} s, ||R|| {res:.2e}, {out[prec]['newton_iterations']} "
               f"Newton / {out[prec]['cg_iterations']} CG iterations", file=sys.stderr, flush=True)
@@ -461,6 +477,9 @@ def main(argv=None):
     ap.add_argument("--mixed", default="box24_q4,box12_q6",
                     help="workloads of the FP64-vs-FP32 apply comparison (the headline one is added)")
     ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--mfma", action="store_true",
+                    help="also time the matrix-core (bf16x3, bf16) sweeps in the mixed leg (slower than FP32 on "
+                         "the vector ALUs at these degrees; not part of the default run)")
     ap.add_argument("--legs", default="apply,mixed,split,hex,newton,learned",
                     help="subset of apply,mixed,split,hex,newton,learned to run (profiling runs; the default runs "
                          "all)")
@@ -482,6 +501,7 @@ def main(argv=None):
 
     cfg = synthetic.get_config(args.workload)
     legs = set(x for x in args.legs.split(",") if x)
+    mixed_precs = ("fp64", "fp32", "bf16x3", "bf16") if args.mfma else ("fp64", "fp32")
     strategies = [s for s in args.strategies.split(",") if s] if "apply" in legs else []
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -597,7 +617,7 @@ def main(argv=None):
     }
     op.close()
     if "mixed" in legs:
-        line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup)
+        line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup, precisions=mixed_precs)
                          for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
     if "split" in legs:
         line["split"] = split_leg(cfg.name, args.steps, args.warmup)
@@ -612,7 +632,7 @@ def main(argv=None):
         line["cpu_baseline"] = cpu_baseline(cfg)
         print("[bench] timing the assembled-CSR product on the host cores", file=sys.stderr, flush=True)
         try:
-            line["cpu_csr"] = cpu_csr_baseline()
+            line["cpu_csr"] = cpu_csr_baseline(cfg)
         except (OSError, RuntimeError) as e:   # a host without the built oracle library or OpenMP
             line["cpu_csr"] = {"value": None, "error": str(e)}
     text = json.dumps(line)

@@ -320,6 +320,15 @@ typedef struct mfe_solve_opts {
                              definite, or larger, the level is smoothed as
                              with 0), 0 = Chebyshev smoothing with
                              coarse_degree and coarse_range */
+    double forcing;       /* Newton: 0 = every CG solve stops at cg_rtol; in (0, 1) =
+                             inexact Newton with the Eisenstat-Walker forcing term
+                             (choice 2, gamma 0.9, exponent 2): the k-th
+                             correction's CG stops at
+                             eta_k = 0.9 (||R_k|| / ||R_k-1||)^2, at least
+                             0.9 eta_(k-1)^2 when that exceeds 0.1, at most
+                             `forcing` (also eta_0), at least cg_rtol and at least
+                             0.5 newton_atol / ||R_k||; the first correction of a
+                             load step (the boundary increment) uses cg_rtol */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64
@@ -390,6 +399,15 @@ int mfe_gmg_apply(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* r_dev,
 /* y = a x + b y on device arrays of n_dofs doubles (vector helper for load
  * stepping drivers: predictors, copies with a = 1, b = 0).  Asynchronous. */
 int mfe_axpby(mfe_ctx* ctx, double a, const double* x_dev, double b, double* y_dev, void* stream);
+
+/* *result_host = x . y over the n_dofs entries of two device arrays, summed in
+ * a fixed order (per-block partial sums, then one ordered sum): the same
+ * inputs give the same bits.  Waits for `stream`. */
+int mfe_dot(mfe_ctx* ctx, const double* x_dev, const double* y_dev, double* result_host, void* stream);
+
+/* v = 0 at the constrained dofs (mfe_set_constraints) of a device array of
+ * n_dofs doubles; no-op without constraints.  Asynchronous. */
+int mfe_zero_constrained(mfe_ctx* ctx, double* v_dev, void* stream);
 
 /* d = diagonal of K(u) at the current state (identity rows: 1 at
  * constrained dofs), from the second-order cache, which this call builds if

@@ -54,7 +54,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
                 ("newton_atol", _d), ("cg_rtol", _d), ("mg_levels", _i), ("cheb_degree", _i),
                 ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d), ("mg_precision", _i),
-                ("mg_graph", _i), ("coarse_direct", _i)]
+                ("mg_graph", _i), ("coarse_direct", _i), ("forcing", _d)]
 
 
 class SolveReport(ctypes.Structure):
@@ -112,6 +112,8 @@ _SIGS = {
     "mfe_net_adam": (_i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     "mfe_gmg_apply": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp]),
     "mfe_axpby": (_i, [_vp, _d, _vp, _d, _vp, _vp]),
+    "mfe_dot": (_i, [_vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "mfe_zero_constrained": (_i, [_vp, _vp, _vp]),
     "mfe_apply_kernel_ms": (_d, [_vp, ctypes.POINTER(_i)]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -331,6 +333,16 @@ def mfe_axpby(ctx, a, x_dev_ptr, b, y_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_axpby(ctx, float(a), x_dev_ptr, float(b), y_dev_ptr, stream))
 
 
+def mfe_dot(ctx, x_dev_ptr, y_dev_ptr, stream=None) -> float:
+    r = _d()
+    _check(ctx, _lib.mfe_dot(ctx, x_dev_ptr, y_dev_ptr, ctypes.byref(r), stream))
+    return r.value
+
+
+def mfe_zero_constrained(ctx, v_dev_ptr, stream=None):
+    return _check(ctx, _lib.mfe_zero_constrained(ctx, v_dev_ptr, stream))
+
+
 def mfe_diagonal(ctx, d_dev_ptr, stream=None):
     return _check(ctx, _lib.mfe_diagonal(ctx, d_dev_ptr, stream))
 
@@ -496,11 +508,12 @@ class Operator:
     @staticmethod
     def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
                    cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=15,
-                   coarse_range=200.0, mg_precision="fp64", mg_graph=1, coarse_direct=1):
+                   coarse_range=200.0, mg_precision="fp64", mg_graph=1, coarse_direct=1, forcing=0.0):
         return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
                          int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol), int(mg_levels),
                          int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range),
-                         PRECISIONS.get(mg_precision, mg_precision), int(mg_graph), int(coarse_direct))
+                         PRECISIONS.get(mg_precision, mg_precision), int(mg_graph), int(coarse_direct),
+                         float(forcing))
 
     def newton_solve(self, u, g=None, stream=None, **opts):
         """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the
@@ -596,16 +609,27 @@ class Operator:
                   _stream_handle(stream))
         return y
 
-    def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, on_step=None, **opts):
+    def dot(self, x, y, stream=None):
+        """x . y (float64 device tensors), summed in a fixed order on the device."""
+        return mfe_dot(self.ctx, _dev_f64(x, self.n_dofs, "x"), _dev_f64(y, self.n_dofs, "y"), _stream_handle(stream))
+
+    def zero_constrained(self, v, stream=None):
+        """v = 0 at the constrained dofs (in place)."""
+        mfe_zero_constrained(self.ctx, _dev_f64(v, self.n_dofs, "v"), _stream_handle(stream))
+        return v
+
+    def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, on_step=None,
+                        extrapolate=True, **opts):
         """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping).
 
         boundary_values(t) -> (dofs, values): prescribed values at load t on the
         constrained dofs.  Steps of 1/n_steps; a step whose Newton solve fails is
-        retried with half the increment (down to min_fraction), and later steps
+        retried from the last converged state instead of the extrapolated one,
+        then with half the increment (down to min_fraction), and later steps
         stay below 0.9 times the smallest increment that failed; the increment
         grows again by 1.25x after each converged step (up to those limits);
         each step starts from the linear extrapolation of the two previous
-        converged states.
+        converged states (extrapolate=True) or from the last converged state.
         u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
         on_step(t, u), if given, is called after every converged step.
         Returns a list of per-step reports (dicts with t, h and the solver report).
@@ -627,10 +651,16 @@ class Operator:
             gh[np.asarray(dofs)] = vals
             g.copy_(torch.from_numpy(gh))
             trial = u.clone()
-            if prev_h is not None:  # trial = u + (h / prev_h) (u - prev)
+            if extrapolate and prev_h is not None:  # trial = u + (h / prev_h) (u - prev)
                 self.axpby(1.0 + h / prev_h, u, 0.0, trial)
                 self.axpby(-h / prev_h, prev, 1.0, trial)
             rep = self.newton_solve(trial, g=g, **opts)
+            if not rep["converged"] and extrapolate and prev_h is not None:
+                # the extrapolated start can be worse than the last converged
+                # state (e.g. cells it distorts): retry the step from there
+                reports.append(dict(t=t + h, h=h, failed=True, **rep))
+                trial.copy_(u)
+                rep = self.newton_solve(trial, g=g, **opts)
             if rep["converged"]:
                 prev.copy_(u)
                 u.copy_(trial)

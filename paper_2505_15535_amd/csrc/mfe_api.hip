@@ -1166,6 +1166,7 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
     }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
+    if (!(o->forcing >= 0.0 && o->forcing < 1.0)) return fail(c, MFE_EINVAL, "forcing must be 0 or in (0, 1)");
     return MFE_OK;
 }
 
@@ -2218,6 +2219,28 @@ int mfe_axpby(mfe_ctx* c, double a, const double* x, double b, double* y, void* 
     return MFE_OK;
 }
 
+int mfe_dot(mfe_ctx* c, const double* x, const double* y, double* result, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!x || !y || !result) return fail(c, MFE_EINVAL, "null pointer");
+    DeviceGuard g(c->device);
+    int rc = ensure_work(c);
+    if (rc != MFE_OK) return rc;
+    double unused;
+    return dotn(c, c->n_dofs, x, y, nullptr, nullptr, static_cast<hipStream_t>(stream), *result, unused);
+}
+
+int mfe_zero_constrained(mfe_ctx* c, double* v, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    if (!v) return fail(c, MFE_EINVAL, "null vector");
+    DeviceGuard g(c->device);
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, v, static_cast<hipStream_t>(stream)));
+    return MFE_OK;
+}
+
 int mfe_diagonal(mfe_ctx* c, double* d, void* stream) {
     if (!c) return MFE_EINVAL;
     c->err.clear();
@@ -2346,6 +2369,8 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
     int status = MFE_ENOTCONV;
     double rn = 0.0;
     bool have_res = false;
+    // Eisenstat-Walker forcing: the previous residual norm and tolerance
+    double rn_prev = 0.0, eta_prev = o->forcing;
     bool boundary_left = has_dg;  // dg holds the part of the Dirichlet increment not yet applied
     for (int it = 0;; ++it) {
         if (!have_res) {
@@ -2378,9 +2403,25 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
             MFE_HIP(c, mfe::launch_axpby(-1.0, du, 1.0, res, n, s));
             MFE_HIP(c, mfe::launch_copy_indexed(c->d_cidx, c->n_con, dg, res, s));
         }
+        mfe_solve_opts oc = *o;
+        if (o->forcing > 0.0 && !boundary_step) {
+            double eta = o->forcing;
+            if (rn_prev > 0.0) {
+                const double q = rn / rn_prev;
+                eta = 0.9 * q * q;
+                const double safe = 0.9 * eta_prev * eta_prev;
+                if (safe > 0.1) eta = std::max(eta, safe);
+            }
+            eta = std::min(eta, o->forcing);
+            eta = std::max(eta, 0.5 * o->newton_atol / rn);
+            eta = std::max(eta, o->cg_rtol);
+            oc.cg_rtol = eta;
+            eta_prev = eta;
+            rn_prev = rn;
+        }
         int iters = 0;
         double rel = 0.0;
-        rc = cg(c, o, res, du, s, iters, rel, &local.pc_fallbacks, &local.net_fallbacks);
+        rc = cg(c, &oc, res, du, s, iters, rel, &local.pc_fallbacks, &local.net_fallbacks);
         local.cg_iterations += iters;
         if (rc != MFE_OK && rc != MFE_ENOTCONV) { status = rc; break; }
         c->err.clear();

@@ -116,21 +116,20 @@ def residuals_at_state(op, cdofs, rng, n_loads=2, cg_stages=(0, 1, 2, 4, 8), opt
     dev = op.device
     op.build_cache("t2")
     op.gmg_setup(**o)
-    cd = torch.from_numpy(np.asarray(cdofs)).to(dev)
     out = []
     for _ in range(n_loads):
         b0 = torch.from_numpy(rng.standard_normal(op.n_dofs)).to(dev)
-        b0[cd] = 0.0
+        op.zero_constrained(b0)
         for j in cg_stages:
-            if j == 0:
-                r = b0.clone()
-            else:
+            r = b0.clone()
+            if j > 0:   # r = b0 - K x after j GMG-CG iterations
                 x, _, _, _ = op.cg_solve(b0, preconditioner="gmg", max_cg=j, cg_rtol=1e-30, **o)
-                r = b0 - op.apply(x, strategy="t2")
+                op.axpby(-1.0, op.apply(x, strategy="t2"), 1.0, r)
             z = op.gmg_apply(r, **o)
-            r1 = r - op.apply(z, strategy="t2")
-            r1[cd] = 0.0
-            out.append(r1 / torch.linalg.norm(r1))
+            r1 = op.axpby(-1.0, op.apply(z, strategy="t2"), 1.0, r)   # r1 = r - K V r
+            op.zero_constrained(r1)
+            op.axpby(0.0, r1, 1.0 / op.dot(r1, r1) ** 0.5, r1)
+            out.append(r1)
     return out
 
 
@@ -166,7 +165,7 @@ def generate(paths, nx=64, ny=16, nz=16, steps=10, states_per_path=8, n_loads=2,
     return out
 
 
-def energy_step(op, net, r1, cd, lr=None):
+def energy_step(op, net, r1, lr=None):
     """J(N) = N.K N / 2 - N.r1 for the correction N of residual r1 at the
     operator's state (T2 cache built); with lr, also one Adam step on J."""
     import torch
@@ -176,11 +175,11 @@ def energy_step(op, net, r1, cd, lr=None):
     mfe_net_forward(net.w.data_ptr(), feat.data_ptr(), P, act.data_ptr(), y.data_ptr(), net.var)
     z = torch.zeros_like(r1)
     op.patch_scatter(y, scale, z)
-    z[cd] = 0.0
+    op.zero_constrained(z)
     Kz = op.apply(z, strategy="t2")
-    J = 0.5 * float(torch.dot(z, Kz)) - float(torch.dot(z, r1))
+    J = 0.5 * op.dot(z, Kz) - op.dot(z, r1)
     if lr is not None:
-        g = Kz - r1
+        g = op.axpby(-1.0, r1, 1.0, Kz)   # K z - r1, in place of Kz
         op.patch_adjoint(g, scale, dy)
         mfe_net_backward(net.w.data_ptr(), feat.data_ptr(), act.data_ptr(), dy.data_ptr(), P, work.data_ptr(),
                          net.g.data_ptr(), net.var)
@@ -210,9 +209,8 @@ def train(data, nx=64, ny=16, nz=16, epochs=10, lr=1e-3, seed=0, device=0, log=N
             smp = samples[si]
             op.set_state(smp.u)
             op.build_cache("t2")
-            cdt = torch.from_numpy(np.asarray(cd)).to(op.device)
             for k in rng.permutation(len(smp.residuals)):
-                tot += energy_step(op, net, smp.residuals[k], cdt, lr)
+                tot += energy_step(op, net, smp.residuals[k], lr)
                 cnt += 1
         hist.append(tot / max(cnt, 1))
         if log:

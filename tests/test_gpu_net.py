@@ -156,7 +156,7 @@ def test_learned_correction_trains_and_is_measured_by_cg(torch_dev):
     ratios = []
     for r1 in rs:
         e1, _, _, _ = op.cg_solve(r1, strategy="t2", preconditioner="gmg", max_cg=500, cg_rtol=1e-10)
-        J = learned.energy_step(op, netw, r1, cdt)
+        J = learned.energy_step(op, netw, r1)
         ratios.append(1.0 + 2.0 * J / float(torch.dot(e1, r1)))
     print("held-out energy ratio (error after / before the correction)", np.round(ratios, 3))
     assert np.mean(ratios) < 1.0

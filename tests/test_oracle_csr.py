@@ -51,3 +51,26 @@ def test_csr_product_random(n, density):
     x = np.random.default_rng(n + 1).standard_normal(n)
     y = _spmv(A, x)
     assert np.allclose(y, A @ x, rtol=1e-14, atol=1e-14)   # empty rows give 0
+
+
+@pytest.mark.parametrize("nx,ny,nz,p,jit", [(4, 4, 4, 2, 0.0), (3, 2, 2, 2, 0.15), (3, 3, 2, 1, 0.15),
+                                           (2, 2, 1, 3, 0.1)])
+def test_c_assembly_matches_numpy_assembly(nx, ny, nz, p, jit):
+    """The C/OpenMP assembly (the benchmark's full-size CSR baseline) against
+    the numpy assembly of the same definition, entry by entry, including the
+    4^3 Q2 cube of the parity workload."""
+    from oracle.assemble_c import assemble_tangent_box
+    rng = np.random.default_rng(nx + 10 * p)
+    v = synthetic.box_vertices(nx, ny, nz, (1.0, 0.9, 0.8), jit, rng)
+    mesh = BoxMesh(nx, ny, nz, p, v)
+    u = synthetic.sine_displacement(nx, ny, nz, p, 0.03, np.random.default_rng(p))
+    K = Problem(mesh, 1.0, 10.0).assemble_tangent(u).tocsr()
+    K.sort_indices()
+    indptr, indices, data, threads = assemble_tangent_box(mesh, 1.0, 10.0, u)
+    assert threads >= 1
+    Kc = sp.csr_matrix((data, indices, indptr), shape=K.shape)
+    # the analytic pattern: every pair of dofs of nodes that share a cell
+    assert np.array_equal(Kc.indptr, K.indptr) and np.array_equal(Kc.indices, K.indices)
+    assert np.max(np.abs(Kc.data - K.data)) <= 1e-13 * np.max(np.abs(K.data))
+    x = np.random.default_rng(4).standard_normal(K.shape[0])
+    assert np.linalg.norm(_spmv(Kc, x) - K @ x) <= 1e-13 * np.linalg.norm(K @ x)
