@@ -9,7 +9,7 @@
 // Templates of the cell kernels, shared by the structured-box instantiations
 // (mfe_kernels.hip) and the general-hexahedral-mesh ones (mfe_kernels_hex.hip).
 //
-// One workgroup processes a brick of neighbouring cells (3x3x1 for Q2), with
+// One workgroup processes a brick of neighbouring cells (4x2x1 for Q2), with
 // one thread per quadrature point of the brick for the point-wise work
 // (Alg. 1/Alg. 2 quadrature loop) and one thread per 1D line of a component
 // for each sum-factorization sweep (Sec. 2.4).  The brick's nodal values are
