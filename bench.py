@@ -40,7 +40,16 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 STRATEGIES = ["otf", "otf_geom", "t2", "t4", "otf_ad"]
 KERNEL_SOURCES = ["paper_2505_15535_amd/csrc/mfe_kernels.hip", "paper_2505_15535_amd/csrc/mfe_kernels_hex.hip",
-                  "paper_2505_15535_amd/csrc/mfe_cell.hpp", "paper_2505_15535_amd/csrc/mfe_device.hpp"]
+                  "paper_2505_15535_amd/csrc/mfe_cell.hpp", "paper_2505_15535_amd/csrc/mfe_device.hpp",
+                  "paper_2505_15535_amd/csrc/mfe_kernels_wave.hip", "paper_2505_15535_amd/csrc/mfe_wave.hpp"]
+
+
+def apply_kernel_name(strategy: str, degree: int, precision: str = "fp64") -> str:
+    """The kernel that runs an apply on a structured box: the wavefront-per-two-
+    cells kernel for Q2 (FP64: cached and dual-number strategies; FP32: all),
+    else the brick kernel."""
+    wave = degree == 2 and (precision == "fp32" or strategy in ("t2", "t4", "otf_ad"))
+    return ("wave_kernel" if wave else "cell_kernel") + f" apply {strategy} {precision}"
 
 
 # --------------------------------------------------------------------------- work model
@@ -251,7 +260,8 @@ def mixed_leg(name, steps, warmup, strategies=("otf", "t2", "t4"), precisions=("
             op.build_cache(s, precision=prec)
             step_ms, kern_ms = time_applies(op, w, v, s, prec, steps, warmup)
             model = work_model(s, cfg.degree, op.n_dofs, op.n_qpoints, nv, elem)
-            rl = roofline(model, kern_ms, None, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS)
+            rl = roofline(model, kern_ms, measured_traffic(name, s if prec == "fp64" else f"{s}/{prec}"),
+                          FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS)
             rec[prec] = {"ms_per_step": round(step_ms, 5), "kernel_ms": round(kern_ms, 5),
                          "gdofs": round(op.n_dofs / (step_ms * 1e-3) / 1e9, 4), "roofline": rl}
             if prec != "fp64":
@@ -418,28 +428,31 @@ def newton_leg(nx=64, ny=16, nz=16, lam=100.0, degrees=90.0, steps=10) -> dict:
 
 
 # --------------------------------------------------------------------------- learned correction
-def learned_leg(nx=64, ny=16, nz=16, epochs=20, variant="relu") -> dict:
-    """Train the learned smoother correction on residuals from load paths with
-    other twist angles and lambda/mu (30 deg / 30, 80 deg / 300, 120 deg / 10),
-    then solve the held-out twisted beam (90 deg, lambda = 100, 10 steps) with
-    GMG and with GMG plus the correction; CG iterations and time for both."""
+def learned_leg(nx=64, ny=16, nz=16, epochs=20, variant="relu", n_paths=8, seed=1) -> dict:
+    """Train the learned smoother step on residuals from load paths with
+    seeded random twist angles (uniform in 30-120 deg) and lambda/mu
+    (log-uniform in 10-1000), two states per path, one random load, CG
+    residuals after 0-8 iterations (about 2e4 patch pairs), then solve the
+    held-out twisted beam (90 deg, lambda = 100, 10 steps) with GMG and with
+    the learned step in the finest post-smoother; CG iterations and time."""
     import numpy as np
     import torch
 
     from paper_2505_15535_amd import learned
 
     t0 = time.perf_counter()
-    data = learned.generate([(30.0, 30.0), (80.0, 300.0), (120.0, 10.0)], nx=nx, ny=ny, nz=nz, steps=6,
-                            states_per_path=4, n_loads=2, seed=1)
+    paths = learned.random_paths(n_paths, seed)
+    data = learned.generate(paths, nx=nx, ny=ny, nz=nz, states_per_path=2, n_loads=1, seed=seed)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     netw, hist = learned.train(data, nx=nx, ny=ny, nz=nz, epochs=epochs, lr=1e-3, seed=0, variant=variant)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    n_res = sum(len(s.residuals) for _, ss in data for s in ss)
+    P = (nx // 4) * (ny // 4) * (nz // 4)
     out = {"workload": f"held-out beam {nx}x{ny}x{nz} Q2, lambda=100, 90 deg in 10 steps",
-           "training": {"paths": "30deg/lambda30, 80deg/lambda300, 120deg/lambda10", "variant": variant,
-                        "samples": sum(len(s.residuals) for _, ss in data for s in ss),
-                        "patches_per_sample": (nx // 4) * (ny // 4) * (nz // 4), "epochs": epochs,
+           "training": {"paths": [[round(a, 2), round(b, 2)] for a, b in paths], "variant": variant,
+                        "residuals": n_res, "patches_per_residual": P, "pairs": n_res * P, "epochs": epochs,
                         "generate_s": round(t_gen, 2), "train_s": round(t_train, 2),
                         "mean_energy_first_last": [hist[0], hist[-1]]}}
     op, bv, cd = learned.beam(nx, ny, nz, 100.0)
@@ -449,7 +462,7 @@ def learned_leg(nx=64, ny=16, nz=16, epochs=20, variant="relu") -> dict:
         op.set_network(netw.params(), variant)  # clears a fallback of an earlier solve
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        reps = op.solve_load_path(u, bv(90.0), 10, **dict(NEWTON_OPTS, preconditioner=pc))
+        reps = op.solve_load_path(u, bv(90.0), 10, extrapolate=False, **dict(NEWTON_OPTS, preconditioner=pc))
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         out[pc] = {"seconds": round(secs, 3),
@@ -611,7 +624,7 @@ def main(argv=None):
         "config": {"workload": cfg.description, "name": cfg.name, "strategy": best, "n_dofs": op.n_dofs,
                    "degree": cfg.degree, "cells": op.n_cells, "qpoints": op.n_qpoints,
                    "mu": cfg.mu, "lambda": cfg.lam, "u_amplitude": cfg.amplitude},
-        "roofline": dict(r["roofline"], kernel=f"cell_kernel apply {best}", kernel_ms=r["kernel_ms"]),
+        "roofline": dict(r["roofline"], kernel=apply_kernel_name(best, cfg.degree), kernel_ms=r["kernel_ms"]),
         "set_state_ms": round(state_ms, 3),
         "strategies": results,
     }

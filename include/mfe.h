@@ -281,15 +281,21 @@ typedef enum mfe_preconditioner {
                              at the nodal interpolant u_l of the state;
                              Chebyshev-Jacobi pre- and post-smoothing;
                              Chebyshev-Jacobi on the coarsest level */
-    MFE_PC_GMG_NET = 3    /* the V-cycle z = V r plus alpha N, N the learned
-                             correction (mfe_set_network) of the residual
-                             r1 = r - K z, alpha = N.r1 / N.K N (the step that
-                             minimises the error's energy norm along N; no step
-                             when either dot is <= 0), inside flexible CG; the
-                             correction is dropped when the residual stagnates
-                             (< 10% reduction over 3 iterations) or r.Br <= 0,
-                             for the rest of that solve and for later solves on
-                             the context until mfe_set_network is called */
+    MFE_PC_GMG_NET = 3    /* the V-cycle with the learned correction
+                             (mfe_set_network) inside the finest level's
+                             post-smoother: its last Chebyshev step is replaced
+                             by x += alpha N, N the network's correction of the
+                             residual r1 = r - K x left by the earlier steps,
+                             alpha = N.r1 / N.K N (the step that minimises the
+                             error's energy norm along N; no step when either
+                             dot is <= 0), formed on the device, so the cycle
+                             stays one kernel sequence (one graph); FP64 V-cycle
+                             only (MFE_EUNSUPPORTED otherwise); inside flexible
+                             CG; the correction is dropped when the residual
+                             stagnates (< 10% reduction over 3 iterations) or
+                             r.Br <= 0, for the rest of that solve and for later
+                             solves on the context until mfe_set_network is
+                             called */
 } mfe_preconditioner;
 
 typedef struct mfe_solve_opts {
@@ -390,7 +396,9 @@ int mfe_cg_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, const double* b_dev, 
  * builds the hierarchy if needed and the level data (states, caches,
  * diagonals, eigenvalue estimates) as a CG solve with MFE_PC_GMG does;
  * mfe_gmg_apply then computes z = B r (r_dev, z_dev: device arrays of n_dofs
- * doubles, not overlapping) with the V-cycle of `opts` (precision, graph).
+ * doubles, not overlapping) with the V-cycle of `opts` (precision, graph),
+ * including the learned step when opts->preconditioner is MFE_PC_GMG_NET
+ * (network set, FP64 V-cycle).
  * MFE_ESTATE if the level data were not set up for the current state and
  * options.  Setup synchronises the stream; apply is asynchronous. */
 int mfe_gmg_setup(mfe_ctx* ctx, const mfe_solve_opts* opts, void* stream);
@@ -457,9 +465,8 @@ double mfe_apply_kernel_ms(mfe_ctx* ctx, int* count_out);
 #define MFE_NET_PARAMS 35491
 /* Network variants: MFE_NET_RELU as above; MFE_NET_LINEAR drops the ReLUs,
  * the biases, the patch scaling (s_p = 1) and the invariant channels (0), so
- * that the correction is a fixed linear map of the residual and the
- * preconditioner a fixed linear operator within a solve (its step alpha is
- * chosen at a solve's first application and then kept). */
+ * that the correction N is a fixed linear map of the residual (the step
+ * alpha is still chosen per application). */
 #define MFE_NET_RELU 0
 #define MFE_NET_LINEAR 1
 

@@ -587,12 +587,14 @@ class Operator:
         """Set up the multigrid level data at the current state (as a GMG CG solve does)."""
         mfe_gmg_setup(self.ctx, self.solve_opts(preconditioner="gmg", **opts), _stream_handle(stream))
 
-    def gmg_apply(self, r, out=None, stream=None, **opts):
-        """out = B r, one application of the GMG preconditioner (after gmg_setup with the same options)."""
+    def gmg_apply(self, r, out=None, stream=None, net=False, **opts):
+        """out = B r, one application of the GMG preconditioner (after gmg_setup with the same options);
+        net=True: with the learned step in the finest post-smoother (set_network first)."""
         import torch
         if out is None:
             out = torch.empty_like(r)
-        mfe_gmg_apply(self.ctx, self.solve_opts(preconditioner="gmg", **opts), _dev_f64(r, self.n_dofs, "r"),
+        pc = "gmg_net" if net else "gmg"
+        mfe_gmg_apply(self.ctx, self.solve_opts(preconditioner=pc, **opts), _dev_f64(r, self.n_dofs, "r"),
                       _dev_f64(out, self.n_dofs, "out"), _stream_handle(stream))
         return out
 

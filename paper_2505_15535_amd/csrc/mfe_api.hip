@@ -340,9 +340,10 @@ struct mfe_ctx {
     // state, per-patch buffers of the preconditioner
     float* d_net = nullptr;
     int net_variant = MFE_NET_RELU;
-    double net_alpha = 0.0;      // linear variant: step length frozen for one CG solve
-    bool net_alpha_set = false;
     bool net_off = false;        // set when a solve had to drop the correction; cleared by mfe_set_network
+    bool net_in_cycle = false;   // the next V-cycle takes the learned step on the finest level
+    bool mg_graph_net = false;   // the captured V-cycle graph holds that step
+    double* d_netdot = nullptr;  // N.r1 and N.K N of the learned step (device)
     float* d_ninv = nullptr;     // [n_nodes][3] I1, I2, J
     float* d_cinv = nullptr;     // [ne][3] scratch
     uint64_t ninv_version = 0;
@@ -418,6 +419,7 @@ void free_mesh_data(mfe_ctx* c) {
     dfree(c->d_ninv);
     dfree(c->d_cinv);
     dfree(c->d_nbuf);
+    dfree(c->d_netdot);
     dfree(c->d_fcg);
     c->ninv_valid = false;
     dfree(c->d_verts);
@@ -1728,6 +1730,8 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
     return MFE_OK;
 }
 
+int net_smooth(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* b, double* x, hipStream_t s);
+
 // x = x + p(D^-1 K) D^-1 (b - K x): `degree` Chebyshev-Jacobi steps on
 // [lmax / range, lmax] with lmax 1.2 times the estimate (x = 0 on entry when
 // zero_start, which saves one operator application).  On the free dofs only:
@@ -1790,6 +1794,15 @@ int vcycle(mfe_ctx* c, const mfe_solve_opts* o, size_t l, const T* b, T* x, hipS
                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), x,
                       static_cast<const T*>(V.dinv), V.r);
     if (rc != MFE_OK) return rc;
+    if constexpr (std::is_same<T, double>::value) {
+        if (l == 0 && c->net_in_cycle) {  // the learned step takes the last post-smoothing step's place
+            if (o->cheb_degree > 1) {
+                rc = chebyshev(c, o, L, b, x, o->cheb_degree - 1, o->cheb_range, false, s);
+                if (rc != MFE_OK) return rc;
+            }
+            return net_smooth(c, o, L, b, x, s);
+        }
+    }
     return chebyshev(c, o, L, b, x, o->cheb_degree, o->cheb_range, false, s);
 }
 
@@ -1821,7 +1834,8 @@ int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, h
     const mfe_solve_opts& go = c->mg_graph_opts;
     const bool same = go.cheb_degree == o->cheb_degree && go.cheb_range == o->cheb_range &&
                       go.coarse_degree == o->coarse_degree && go.coarse_range == o->coarse_range &&
-                      go.coarse_direct == o->coarse_direct && go.strategy == o->strategy;
+                      go.coarse_direct == o->coarse_direct && go.strategy == o->strategy &&
+                      c->mg_graph_net == c->net_in_cycle;
     if (!c->mg_graph_valid || !same || c->mg_graph_r != r || c->mg_graph_z != z ||
         c->mg_graph_prec != o->mg_precision) {
         if (c->mg_exec) {
@@ -1849,6 +1863,7 @@ int gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, h
         c->mg_graph_z = z;
         c->mg_graph_prec = o->mg_precision;
         c->mg_graph_opts = *o;
+        c->mg_graph_net = c->net_in_cycle;
     }
     MFE_HIP(c, hipGraphLaunch(c->mg_exec, s));
     return MFE_OK;
@@ -1919,63 +1934,70 @@ int ensure_node_invariants(mfe_ctx* c, hipStream_t s) {
     return MFE_OK;
 }
 
-// z += alpha N, the learned correction N of the residual r1 = r - K z left by
-// the V-cycle (z holds V r): features of every patch, the network, the
-// patch-averaged scatter, N = 0 at constrained dofs; alpha = N.r1 / N.K N
-// minimises the energy norm of the error along N, so the step never makes
-// the error larger (it is skipped when N.r1 <= 0 or N.K N <= 0).
-int net_correct(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* z, hipStream_t s) {
+// Buffers and state data of the learned step, set up outside the V-cycle
+// (which may be captured in a graph): the node invariants of the current
+// state, the per-patch buffers and the device slots of its two dots.
+int net_prepare(mfe_ctx* c, hipStream_t s) {
     int npx, npy, npz;
     const int P = patch_dims(c, npx, npy, npz);
-    const int64_t n = c->n_dofs;
-    double* Kv = c->d_work + 9 * n;   // K z, then K N
-    double* r1 = c->d_work + 10 * n;  // r - K z
-    double* N = c->d_work + 8 * n;    // the correction
+    if (!c->d_net) return fail(c, MFE_EINVAL, "no network set (mfe_set_network)");
+    if (P == 0) return fail(c, MFE_EUNSUPPORTED, "the learned correction needs Q2 and cell counts divisible by 4");
     int rc = ensure_node_invariants(c, s);
     if (rc != MFE_OK) return rc;
     const int64_t per = (int64_t)P * kPatchVox;
     if (!c->d_nbuf) MFE_HIP(c, hipMalloc(&c->d_nbuf, ((6 + 64 + 3) * per + P) * sizeof(float)));
+    if (!c->d_netdot) MFE_HIP(c, hipMalloc(&c->d_netdot, 2 * sizeof(double)));
+    return MFE_OK;
+}
+
+// The learned step of the finest level's post-smoother (in place of its last
+// Chebyshev step): r1 = b - K x, the residual the earlier smoothing left on
+// the free dofs; N = the network's correction of r1 (features of every
+// patch, the network, the patch-averaged scatter, 0 at constrained dofs);
+// x += alpha N with alpha = N.r1 / N.K N, the step that minimises the energy
+// norm of the error along N (no step unless both dots are positive).  The
+// dots stay on the device and alpha is formed there, so the V-cycle remains
+// one kernel sequence without host synchronisation.
+int net_smooth(mfe_ctx* c, const mfe_solve_opts* o, MGLevel& L, const double* b, double* x, hipStream_t s) {
+    int npx, npy, npz;
+    const int P = patch_dims(c, npx, npy, npz);
+    const int64_t n = c->n_dofs;
+    double* N = c->d_work + 8 * n;    // the correction
+    double* Kv = c->d_work + 9 * n;   // K x, then K N
+    double* r1 = c->d_work + 10 * n;  // b - K x
+    const int64_t per = (int64_t)P * kPatchVox;
     float* feat = c->d_nbuf;
     float* act = feat + 6 * per;
     float* y = act + 64 * per;
     float* scale = y + 3 * per;
-    rc = mfe_apply_tangent(c, z, Kv, o->strategy, MFE_FP64, s);
+    MFE_HIP(c, mfe::launch_fill(Kv, n, 0.0, s));
+    int rc = level_apply(c, o, L, static_cast<const double*>(x), Kv, s);
     if (rc != MFE_OK) return rc;
-    MFE_HIP(c, mfe::launch_copy(r, r1, n, s));
+    MFE_HIP(c, mfe::launch_copy(b, r1, n, s));
     MFE_HIP(c, mfe::launch_axpby(-1.0, Kv, 1.0, r1, n, s));
+    if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, r1, s));
     const bool linear = c->net_variant == MFE_NET_LINEAR;
     MFE_HIP(c, mfe::launch_patch_features(r1, c->d_ninv, c->Nx, c->Ny, npx, npy, P, linear, feat, scale, s));
     MFE_HIP(c, net_forward(c->d_net, feat, P, c->net_variant, act, y, s));
     MFE_HIP(c, mfe::launch_fill(N, n, 0.0, s));
     MFE_HIP(c, mfe::launch_patch_scatter(y, scale, c->Nx, c->Ny, c->Nz, npx, npy, npz, 1.0, N, s));
     if (c->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(c->d_cidx, c->n_con, 0.0, N, s));
-    if (linear && c->net_alpha_set) {  // a fixed linear preconditioner within the solve
-        if (c->net_alpha > 0.0) MFE_HIP(c, mfe::launch_axpby(c->net_alpha, N, 1.0, z, n, s));
-        return MFE_OK;
-    }
-    rc = mfe_apply_tangent(c, N, Kv, o->strategy, MFE_FP64, s);
+    MFE_HIP(c, mfe::launch_fill(Kv, n, 0.0, s));
+    rc = level_apply(c, o, L, static_cast<const double*>(N), Kv, s);
     if (rc != MFE_OK) return rc;
-    double nr, nkn;
-    rc = dot2(c, N, r1, N, Kv, s, nr, nkn);
-    if (rc != MFE_OK) return rc;
-    const bool ok = nr > 0.0 && nkn > 0.0 && std::isfinite(nr) && std::isfinite(nkn);
-    if (ok) MFE_HIP(c, mfe::launch_axpby(nr / nkn, N, 1.0, z, n, s));
-    if (linear) {
-        c->net_alpha = ok ? nr / nkn : 0.0;
-        c->net_alpha_set = true;
-    }
+    MFE_HIP(c, mfe::launch_dot2(N, r1, N, Kv, n, c->d_partials, c->d_netdot, s));
+    MFE_HIP(c, mfe::launch_axpy_ratio(c->d_netdot, N, x, n, s));
     return MFE_OK;
 }
 
-// z = B r (GMG V-cycle, plus the learned correction when `net`), then r.z > 0
+// z = B r (GMG V-cycle, with the learned step in its finest post-smoother
+// when `net`), then r.z > 0
 int precondition(mfe_ctx* c, const mfe_solve_opts* o, bool net, const double* r, double* z, hipStream_t s,
                  double& rz) {
+    c->net_in_cycle = net;
     int rc = gmg_apply(c, o, r, z, s);
+    c->net_in_cycle = false;
     if (rc != MFE_OK) return rc;
-    if (net) {
-        rc = net_correct(c, o, r, z, s);
-        if (rc != MFE_OK) return rc;
-    }
     double unused;
     rc = dot2(c, r, z, nullptr, nullptr, s, rz, unused);
     if (rc != MFE_OK) return rc;
@@ -2079,10 +2101,11 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
     int rc;
     if (net) {
         int npx, npy, npz;
-        c->net_alpha_set = false;  // a new solve: the linear variant's step is chosen again
         if (!c->d_net) return fail(c, MFE_EINVAL, "no network set (mfe_set_network)");
         if (patch_dims(c, npx, npy, npz) == 0)
             return fail(c, MFE_EUNSUPPORTED, "the learned correction needs Q2 and cell counts divisible by 4");
+        if (o->mg_precision != MFE_FP64)
+            return fail(c, MFE_EUNSUPPORTED, "the learned correction runs in the FP64 V-cycle");
     }
     MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
     MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, b, r, n, s));
@@ -2094,6 +2117,7 @@ int cg(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x, hipStrea
         rc = mg_build(c, o->mg_levels);
         if (rc != MFE_OK) return rc;
         rc = mg_update(c, o, s);
+        if (rc == MFE_OK && net) rc = net_prepare(c, s);
         if (rc == MFE_OK) {
             double unused;
             rc = precondition(c, o, net, r, z, s, unused);
@@ -2305,8 +2329,17 @@ int mfe_gmg_apply(mfe_ctx* c, const mfe_solve_opts* o, const double* r, double* 
     const int64_t n = c->n_dofs;
     double* rw = c->d_work;      // the CG residual and preconditioned residual slots:
     double* zw = c->d_work + n;  // the same buffers as inside CG, so one graph serves both
+    const bool net = o->preconditioner == MFE_PC_GMG_NET;
+    if (net) {
+        if (o2.mg_precision != MFE_FP64)
+            return fail(c, MFE_EUNSUPPORTED, "the learned correction runs in the FP64 V-cycle");
+        rc = net_prepare(c, s);
+        if (rc != MFE_OK) return rc;
+    }
     MFE_HIP(c, mfe::launch_copy(r, rw, n, s));
+    c->net_in_cycle = net;
     rc = gmg_apply(c, &o2, rw, zw, s);
+    c->net_in_cycle = false;
     if (rc != MFE_OK) return rc;
     MFE_HIP(c, mfe::launch_copy(static_cast<const double*>(zw), z, n, s));
     return MFE_OK;

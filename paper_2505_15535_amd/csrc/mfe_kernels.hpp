@@ -157,6 +157,9 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, const 
 hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* Ap, const double* dinv,
                             double alpha, int64_t n, double* partials, double* out, hipStream_t s);
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+// x += (nd[0] / nd[1]) y, the ratio read on the device (no update unless both
+// are positive and the ratio finite)
+hipError_t launch_axpy_ratio(const double* nd, const double* y, double* x, int64_t n, hipStream_t s);
 // launch_cg_update with alpha = rz[0] / pAp[0] read on the device (alpha = 0,
 // so x and r unchanged, unless both are positive)
 hipError_t launch_cg_update_dev(double* x, double* r, double* z, const double* p, const double* Ap,

@@ -129,6 +129,17 @@ __global__ void p_update_dev_kernel(const double* __restrict__ z, const double* 
         p[i] = fma(1.0, z[i], beta * p[i]);
 }
 
+// x += (nd[0] / nd[1]) y when both are positive and the ratio is finite
+__global__ void axpy_ratio_kernel(const double* __restrict__ nd, const double* __restrict__ y, double* __restrict__ x,
+                                  int64_t n) {
+    const double num = nd[0], den = nd[1];
+    double a = (num > 0.0 && den > 0.0) ? num / den : 0.0;
+    if (!isfinite(a)) a = 0.0;
+    if (a == 0.0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = fma(a, y[i], x[i]);
+}
+
 // y = a x + b y
 __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -246,6 +257,11 @@ hipError_t launch_multi_axpy(const double* z, const double* P, const DirCoeffs& 
 
 hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kRedThreads), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_ratio(const double* nd, const double* y, double* x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_ratio_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, nd, y, x, n);
     return hipGetLastError();
 }
 

@@ -1,18 +1,22 @@
 """Training data, training loop and evaluation of the learned smoother
 correction (preconditioner "gmg_net").
 
-The correction acts after a GMG V-cycle: with z = V r, the residual left is
-r1 = r - K z, and the network maps the patch features of r1 (residual scaled
-by its patch RMS, strain invariants of the state) to a correction N(r1),
-assembled from the patch outputs by averaging over shared nodes.  Its quality
+The correction is a step of the finest level's post-smoother (it replaces
+the last Chebyshev step): with x the V-cycle's iterate before that step, the
+residual left is r1 = r - K x, and the network maps the patch features of r1
+(residual scaled by its patch RMS, strain invariants of the state) to a
+correction N(r1), assembled from the patch outputs by averaging over shared
+nodes; the cycle adds alpha N with the energy-optimal alpha.  Its quality
 is the energy norm of the error it leaves, ||e1 - N||_K^2 with e1 = K^-1 r1,
 which equals 2 J(N) + e1.r1 with J(N) = N.K N / 2 - N.r1: the loss is J, the
 potential energy of the correction, whose gradient K N - r1 is the residual
 after the correction -- no solved target is needed, and the norm weights the
 local (high-frequency) part of the error that a patch network can represent,
 not the smooth part that the coarse grid already handles.  Residuals r1 come
-from the Newton-CG solver itself: states along twisted-beam load paths, CG
-residuals of random loads after 0-8 GMG-CG iterations, one V-cycle applied.
+from the Newton-CG solver itself: states along twisted-beam load paths with
+seeded random twist angles and lambda/mu (random_paths), CG residuals of
+random loads after 0-8 GMG-CG iterations, one V-cycle applied up to the
+learned step (the cycle with a zero network, whose step is then empty).
 Every arithmetic step runs in the library's kernels (V-cycle, applies,
 features, scatter and its adjoint, the network's forward and backward passes,
 Adam); torch only holds the buffers.
@@ -106,14 +110,26 @@ def beam(nx, ny, nz, lam, device=0):
     return op, bv, cd
 
 
+def random_paths(n, seed, theta=(30.0, 120.0), lam=(10.0, 1000.0)):
+    """n load paths (theta_deg, lambda/mu): theta uniform, lambda/mu log-uniform in the given ranges."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(theta[0], theta[1], n)
+    lm = np.exp(rng.uniform(np.log(lam[0]), np.log(lam[1]), n))
+    return [(float(a), float(b)) for a, b in zip(th, lm)]
+
+
 def residuals_at_state(op, cdofs, rng, n_loads=2, cg_stages=(0, 1, 2, 4, 8), opts=None):
-    """Unit-norm residuals r1 = r - K V r left by one V-cycle, for r = CG
-    residuals of random loads after 0, 1, 2, 4, 8 GMG-CG iterations, at the
-    operator's current state (T2 cache and level data are built here)."""
+    """Unit-norm residuals r1 = r - K V' r, V' the V-cycle up to the learned
+    step (the cycle run with a zero network), for r = CG residuals of random
+    loads after 0, 1, 2, 4, 8 GMG-CG iterations, at the operator's current
+    state (T2 cache and level data are built here; the operator's network is
+    replaced by zeros)."""
     import torch
+    from . import MFE_NET_PARAMS
     o = dict(strategy="t2", mg_precision="fp64")
     o.update(opts or {})
     dev = op.device
+    op.set_network(np.zeros(MFE_NET_PARAMS, dtype=np.float32))
     op.build_cache("t2")
     op.gmg_setup(**o)
     out = []
@@ -125,8 +141,8 @@ def residuals_at_state(op, cdofs, rng, n_loads=2, cg_stages=(0, 1, 2, 4, 8), opt
             if j > 0:   # r = b0 - K x after j GMG-CG iterations
                 x, _, _, _ = op.cg_solve(b0, preconditioner="gmg", max_cg=j, cg_rtol=1e-30, **o)
                 op.axpby(-1.0, op.apply(x, strategy="t2"), 1.0, r)
-            z = op.gmg_apply(r, **o)
-            r1 = op.axpby(-1.0, op.apply(z, strategy="t2"), 1.0, r)   # r1 = r - K V r
+            z = op.gmg_apply(r, net=True, **o)
+            r1 = op.axpby(-1.0, op.apply(z, strategy="t2"), 1.0, r)   # r1 = r - K V' r
             op.zero_constrained(r1)
             op.axpby(0.0, r1, 1.0 / op.dot(r1, r1) ** 0.5, r1)
             out.append(r1)
@@ -141,9 +157,12 @@ class Sample:
         self.residuals = residuals
 
 
-def generate(paths, nx=64, ny=16, nz=16, steps=10, states_per_path=8, n_loads=2, seed=0, device=0, log=None):
-    """Samples along load paths [(theta_deg, lam), ...] of the twisted beam;
-    returns [(lam, [Sample, ...]), ...]."""
+def generate(paths, nx=64, ny=16, nz=16, steps=None, states_per_path=8, n_loads=2, seed=0, device=0, log=None,
+             cg_stages=(0, 1, 2, 4, 8)):
+    """Samples along load paths [(theta_deg, lam), ...] of the twisted beam
+    (in `steps` load steps, default one per 9 degrees);
+    returns [(lam, [Sample, ...]), ...] (each sample: one state and
+    n_loads * len(cg_stages) residuals, each giving one pair per patch)."""
     import torch
     rng = np.random.default_rng(seed)
     out = []
@@ -151,13 +170,15 @@ def generate(paths, nx=64, ny=16, nz=16, steps=10, states_per_path=8, n_loads=2,
         op, bv, cd = beam(nx, ny, nz, lam, device)
         u = torch.zeros(op.n_dofs, dtype=torch.float64, device=op.device)
         states = []
-        op.solve_load_path(u, bv(theta), steps, on_step=lambda t, uu: states.append(uu.clone()),
-                           strategy="t2", preconditioner="gmg", max_newton=8, cg_rtol=1e-3)
+        n_steps = steps if steps else max(1, int(np.ceil(theta / 9.0)))
+        op.solve_load_path(u, bv(theta), n_steps, on_step=lambda t, uu: states.append(uu.clone()),
+                           extrapolate=False, strategy="t2", preconditioner="gmg", max_newton=30, cg_rtol=1e-3,
+                           forcing=0.5)
         pick = np.linspace(0, len(states) - 1, min(states_per_path, len(states))).round().astype(int)
         samples = []
         for k in pick:
             op.set_state(states[k])
-            samples.append(Sample(states[k], residuals_at_state(op, cd, rng, n_loads=n_loads)))
+            samples.append(Sample(states[k], residuals_at_state(op, cd, rng, n_loads=n_loads, cg_stages=cg_stages)))
         out.append((lam, samples))
         if log:
             log(f"path theta={theta:.1f} lam={lam:.1f}: {len(states)} states, {len(samples)} sampled")

@@ -1,6 +1,7 @@
 """The learned smoother correction: the network's forward and backward
 kernels against the FP64 oracle (oracle/net.py), the Adam kernel, the patch
-gather/scatter, and the preconditioner trained on pairs the solver generates.
+gather/scatter, and the learned step of the multigrid smoother trained on
+pairs the solver generates.
 
 Tolerances: forward 1e-5 and gradients 1e-4 (relative 2-norm): FP32 sums of
 up to 32*27 = 864 terms per output and of 729*P products per weight
@@ -133,44 +134,66 @@ def test_patch_gather_scatter_and_invariants(torch_dev):
     assert cnt.max() == 2 and cnt.min() == 1
 
 
-def test_learned_correction_trains_and_is_measured_by_cg(torch_dev):
-    """Train on residuals from two load paths of a 16x8x8 beam and evaluate on a
-    held-out path (lambda = 100, 60 degrees): the energy of the error the
-    V-cycle leaves must drop on held-out residuals; CG with the correction
-    must reach the same tolerance with a true residual to match; the
-    iteration counts with and without it are printed (the gain)."""
+def test_learned_step_in_the_smoother(torch_dev):
+    """Train on residuals from seeded random load paths of a 16x8x8 beam
+    (twist 30-120 degrees, lambda/mu log-uniform in 10-1000) and evaluate at
+    a held-out state (lambda = 100, 60 degrees).  The learned step in the
+    finest post-smoother is the energy-optimal step along N, so the cycle
+    with it never leaves a larger error energy than the cycle stopped before
+    it (the same cycle with a zero network); on held-out residuals it also
+    leaves less than the plain cycle with all its Chebyshev steps.  The
+    step's graph replay matches the launch-by-launch cycle; CG with it
+    reaches the tolerance with a true residual to match; the CG iteration
+    counts with and without it are printed."""
     import paper_2505_15535_amd as mfe
     from paper_2505_15535_amd import learned
     torch, dev = torch_dev
-    data = learned.generate([(45.0, 30.0), (70.0, 300.0)], nx=16, ny=8, nz=8, steps=4, states_per_path=3,
-                            n_loads=2, seed=1)
+    paths = learned.random_paths(3, 5)
+    assert all(30.0 <= t <= 120.0 and 10.0 <= l <= 1000.0 for t, l in paths)
+    data = learned.generate(paths, nx=16, ny=8, nz=8, steps=3, states_per_path=2, n_loads=2, seed=1)
     netw, hist = learned.train(data, nx=16, ny=8, nz=8, epochs=25, lr=1e-3, seed=0)
     print("mean J per epoch", [f"{h:.3e}" for h in hist])
     assert hist[-1] < 0.0 and min(hist) < hist[0]
     op, bv, cd = learned.beam(16, 8, 8, 100.0)
     cdt = torch.from_numpy(cd).to(dev)
     u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
-    op.solve_load_path(u, bv(60.0), 3, strategy="t2", preconditioner="gmg", max_newton=8, cg_rtol=1e-3)
+    op.solve_load_path(u, bv(60.0), 3, strategy="t2", preconditioner="gmg", max_newton=20, cg_rtol=1e-3)
     op.set_state(u)
-    rs = learned.residuals_at_state(op, cd, np.random.default_rng(7), n_loads=1)
-    ratios = []
-    for r1 in rs:
-        e1, _, _, _ = op.cg_solve(r1, strategy="t2", preconditioner="gmg", max_cg=500, cg_rtol=1e-10)
-        J = learned.energy_step(op, netw, r1)
-        ratios.append(1.0 + 2.0 * J / float(torch.dot(e1, r1)))
-    print("held-out energy ratio (error after / before the correction)", np.round(ratios, 3))
-    assert np.mean(ratios) < 1.0
-    op.set_network(netw.params())
+    o = dict(strategy="t2", mg_precision="fp64")
+    rs = learned.residuals_at_state(op, cd, np.random.default_rng(7), n_loads=1)   # leaves a zero network set
+
+    def energy(e, z, r):   # ||e - z||_K^2 / ||e||_K^2
+        d = e - z
+        return float(torch.dot(d, op.apply(d, strategy="t2"))) / float(torch.dot(e, r))
+
+    rows = []
+    for r in rs:
+        e, _, _, _ = op.cg_solve(r, strategy="t2", preconditioner="gmg", max_cg=500, cg_rtol=1e-11)
+        op.set_network(np.zeros(mfe.MFE_NET_PARAMS, dtype=np.float32))
+        z_stop = op.gmg_apply(r, net=True, **o)            # the cycle stopped before the learned step
+        op.set_network(netw.params())
+        z_net = op.gmg_apply(r, net=True, **o)
+        z_net0 = op.gmg_apply(r, net=True, mg_graph=0, **o)
+        assert float(torch.linalg.norm(z_net - z_net0) / torch.linalg.norm(z_net)) < 1e-10
+        z_plain = op.gmg_apply(r, **o)
+        rows.append((energy(e, z_stop, r), energy(e, z_net, r), energy(e, z_plain, r)))
+    rows = np.array(rows)
+    print("error energy after the cycle: stopped before the step / with the learned step / plain\n", rows.round(4))
+    assert np.all(rows[:, 1] <= rows[:, 0] * (1.0 + 1e-9))
+    assert rows[:, 1].mean() < rows[:, 2].mean()
     b = torch.from_numpy(np.random.default_rng(9).standard_normal(op.n_dofs)).to(dev)
     b[cdt] = 0.0
     res = {}
     for pc in ("gmg", "gmg_net"):
+        op.set_network(netw.params())
         x, it, rel, st = op.cg_solve(b, strategy="t2", preconditioner=pc, max_cg=500, cg_rtol=1e-8)
         true = float(torch.linalg.norm(b - op.apply(x, strategy="t2")) / torch.linalg.norm(b))
         res[pc] = (it, true, st)
     print("CG iterations, true relative residual:", res)
     for pc in res:
         assert res[pc][2] == "MFE_OK" and res[pc][1] <= 2e-8
+    with pytest.raises(mfe.MfeError):   # the learned step runs in the FP64 V-cycle only
+        op.cg_solve(b, strategy="t2", preconditioner="gmg_net", mg_precision="fp32", max_cg=50, cg_rtol=1e-3)
 
 
 def test_bad_network_falls_back(torch_dev):
