@@ -604,7 +604,11 @@ def main(argv=None):
             line["newton"] = newton_leg()
         if "learned" in legs:
             line["learned"] = learned_leg()
-        print(json.dumps(line), flush=True)
+        text = json.dumps(line)
+        print(text, flush=True)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(text + "\n")
         return 0
     best = max(results, key=lambda k: results[k]["gdofs"])
     r = results[best]
