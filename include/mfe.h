@@ -81,12 +81,15 @@ typedef enum mfe_strategy {
 /* Arithmetic of the tangent apply (the precision direction of the method's
  * growth: the sweeps inside a preconditioner need not be FP64).
  *   MFE_FP64     w, v double; everything FP64.
- *   MFE_SF_FP32  w, v float; the sum-factorization sweeps of w and the test
- *                contraction in FP32, FP32 atomics; T2/T4 applies read the
- *                FP32 cache (mfe_build_cache_fp32: values computed in FP64 from
- *                F, J, log J and rounded once, all products FP32); on-the-fly
- *                strategies keep u, F, J, log J and the point-wise response in
- *                FP64 and round the result to FP32 before the contraction.
+ *   MFE_SF_FP32  w, v float, FP32 atomics; T2/T4 applies read the FP32
+ *                cache (mfe_build_cache_fp32: values computed in FP64 from
+ *                F, J, log J and rounded once) and run the sweeps of w, the
+ *                point-wise products and the test contraction in FP32; the
+ *                on-the-fly strategies keep u, F, J, log J, the point-wise
+ *                response and the sweeps of w in FP64 (FP32 sweeps only for
+ *                MFE_OTF_GEOM on Q2 boxes and in the coloured mode), since
+ *                they are bound by arithmetic that FP32 does not make
+ *                cheaper without packed instructions.
  *   MFE_SF_BF16  as MFE_SF_FP32 (float w and v, the FP32 cache of
  *                mfe_build_cache_fp32), but the sum-factorization sweeps of w
  *                and the test contraction run on the matrix cores: 16x16x16

@@ -978,7 +978,7 @@ static int apply_impl(mfe_ctx* c, const void* w, void* v, int strategy, int prec
     // constrained dofs itself; the others read a masked copy of w and get the
     // constrained entries of v copied afterwards
     // (the coloured mode always runs it)
-    const bool wave = mfe::wave_apply(c->tab.n, mode, c->hex, sweep, fp32 || c->deterministic);
+    const bool wave = mfe::wave_apply(c->tab.n, mode, c->hex, sweep, fp32, c->deterministic);
     if (c->deterministic && !wave)
         return fail(c, MFE_EUNSUPPORTED, "the coloured apply is built for Q2 structured boxes with vector-ALU sweeps");
     if (fp32) {

@@ -15,9 +15,9 @@
 // for each sum-factorization sweep (Sec. 2.4).  The brick's nodal values are
 // gathered once with coalesced row loads into LDS; intermediate tensors are
 // staged in LDS with workgroup barriers between sweep stages.  The cells'
-// contributions are summed in LDS, then written with plain stores for nodes
-// inside the brick and FP64 atomics for nodes on its faces.  Per-point caches
-// are stored brick-major so that a workgroup streams one contiguous range.
+// contributions are summed in LDS, then every node of the brick is added to
+// v with one atomic.  Per-point caches are stored brick-major so that a
+// workgroup streams one contiguous range.
 //
 // Sum factorization (collocation form): nodal values are interpolated to the
 // Gauss points with three sweeps of S (x, y, z), then the reference gradient
@@ -204,12 +204,12 @@ __device__ __forceinline__ void brick_load(const R* __restrict__ src, const Bric
     for (int k = 0; k < Geo<N, HX>::GPT; ++k) r[k] = (m.exists >> k & 1u) ? src[m.dof[k]] : R(0);
 }
 
-template <int N, bool HX, typename R>
-__device__ __forceinline__ void brick_store(R* sBrick, const R (&r)[Geo<N, HX>::GPT]) {
+template <int N, bool HX, typename L, typename R>
+__device__ __forceinline__ void brick_store(L* sBrick, const R (&r)[Geo<N, HX>::GPT]) {
 #pragma unroll
     for (int k = 0; k < Geo<N, HX>::GPT; ++k) {
         const int e = threadIdx.x + k * Geo<N, HX>::NT;
-        if (e < Geo<N, HX>::BRICK) sBrick[e] = r[k];
+        if (e < Geo<N, HX>::BRICK) sBrick[e] = (L)r[k];
     }
 }
 
@@ -322,29 +322,30 @@ __device__ __forceinline__ void forward_sweeps(const BrickPos& bp, const Tables<
     __syncthreads();
 }
 
-// The brick's summed node values (sBrick, made visible by a barrier) added to
-// dst: plain stores for nodes inside the brick, FP64/FP32 atomics on its faces.
-template <int N, bool HX, typename R>
-__device__ __forceinline__ void brick_scatter(R* __restrict__ dst, const BrickMap<N, HX>& bm, const R* sBrick) {
+// The brick's summed node values (sBrick, made visible by a barrier, type R)
+// added to dst (type D) with one atomic per node.  Every node takes an
+// atomic, also those inside the brick that no other brick touches: plain
+// stores into cache lines that neighbouring bricks update atomically cost
+// more than the atomics (T2 at Q4 71 against 56 us).
+template <int N, bool HX, typename D, typename R>
+__device__ __forceinline__ void brick_scatter(D* __restrict__ dst, const BrickMap<N, HX>& bm, const R* sBrick) {
 #pragma unroll
     for (int k = 0; k < Geo<N, HX>::GPT; ++k) {
         if (!(bm.exists >> k & 1u)) continue;
         const R val = sBrick[threadIdx.x + k * Geo<N, HX>::NT];
-        if (bm.face >> k & 1u) unsafeAtomicAdd(dst + bm.dof[k], val);
-        else dst[bm.dof[k]] = val;
+        unsafeAtomicAdd(dst + bm.dof[k], (D)val);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Backward sweeps: on entry slot d of sG holds Q[c][d] at every point (made
 // visible by a barrier) and sBrick is zero.  Adds
-// sum_q sum_d Q[c][d](q) dN_a/dxi_d(q) of every cell to dst.  The cells'
-// contributions are summed in LDS; nodes inside the brick are then written
-// with plain stores, nodes on its faces (shared with neighbouring bricks)
-// with FP64 atomics.
+// sum_q sum_d Q[c][d](q) dN_a/dxi_d(q) of every cell to dst (sweeps in R,
+// dst of type D).  The cells' contributions are summed in LDS, then every
+// node of the brick is added to dst with an atomic.
 // ---------------------------------------------------------------------------
-template <int N, bool HX, typename R>
-__device__ __forceinline__ void backward_sweeps(R* __restrict__ dst, const BrickPos& bp, const BrickMap<N, HX>& bm,
+template <int N, bool HX, typename R, typename D>
+__device__ __forceinline__ void backward_sweeps(D* __restrict__ dst, const BrickPos& bp, const BrickMap<N, HX>& bm,
                                                 const Tables<N, R>& T, R* sG, R* sV, R* sBrick,
                                                 const unsigned short* sL) {
     using G = Geo<N, HX>;
@@ -701,9 +702,13 @@ struct ModeInfo {
 #ifndef MFE_MIN_WAVES_PER_EU
 #define MFE_MIN_WAVES_PER_EU 1
 #endif
-// Vector and cache element types of a launch: R is the type of w, v, the
-// T2/T4 caches and the sweeps of the w field; the u field, the geometry and
-// the per-point kinematics are always FP64.
+// Vector and cache element types of a launch: R is the type of w, v and the
+// T2/T4 caches; the u field, the geometry and the per-point kinematics are
+// always FP64.  The sweeps of the w field run in R for the cached strategies
+// and in FP64 for the on-the-fly ones: they are bound by their arithmetic,
+// and without packed FP32 arithmetic (which the build disables) an FP32
+// vector instruction costs what an FP64 one does, so FP32 sweeps would only
+// add conversions around the FP64 point-wise response.
 template <typename R>
 __device__ __forceinline__ const R* w_of(const KParams& p) {
     if constexpr (std::is_same_v<R, float>) return p.w32; else return p.w;
@@ -735,6 +740,9 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
     // type of the cached per-point data read by an apply
     constexpr bool cached_r = MODE == MODE_APPLY_T2 || MODE == MODE_APPLY_T4;
     using CT = std::conditional_t<cached_r, R, double>;
+    // type of the sweeps of the w field (FP64 in the on-the-fly modes, whose
+    // LDS arrays are FP64 for the u field anyway)
+    using WT = std::conditional_t<MI::fwd_u && SW == 0, double, R>;
     __shared__ LT sG[G::NQ * 9];
     __shared__ LT sV[G::NQ * 3];
     __shared__ LT sBrick[G::BRICK];
@@ -926,19 +934,22 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
     }
 
     // ---------------- field w and the point-wise product
-    R* gW = reinterpret_cast<R*>(sG);
-    R* vW = reinterpret_cast<R*>(sV);
-    R* bW = reinterpret_cast<R*>(sBrick);
-    R Q[3][3] = {};
+    WT* gW = reinterpret_cast<WT*>(sG);
+    WT* vW = reinterpret_cast<WT*>(sV);
+    WT* bW = reinterpret_cast<WT*>(sBrick);
+    const auto& TW = [&]() -> const Tables<N, WT>& {
+        if constexpr (std::is_same_v<WT, R>) return TR; else return T;
+    }();
+    WT Q[3][3] = {};
     if constexpr (MI::fwd_w) {
         // sBrick was last read before the forward sweeps' first barrier
         brick_store<N, HX>(bW, wb);
         __syncthreads();
         if constexpr (SW > 0) forward_sweeps_mfma<N, HX, SW>(bp, MM, gW, vW, bW, sL);
-        else forward_sweeps<N, HX>(bp, TR, gW, vW, bW, true, sL);
+        else forward_sweeps<N, HX>(bp, TW, gW, vW, bW, true, sL);
         if constexpr (MODE != MODE_APPLY_OTF_GEOM) load_late();
         if (active) {
-            R dwr[3][3];
+            WT dwr[3][3];
             load_slots<N>(gW, tid, dwr);
             if constexpr (MODE == MODE_APPLY_OTF || MODE == MODE_APPLY_OTF_GEOM || MI::otf_ad) {
                 // the point-wise response is evaluated in FP64
@@ -954,7 +965,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) Q[i][j] = (R)Qd[i][j];
+                    for (int j = 0; j < 3; ++j) Q[i][j] = (WT)Qd[i][j];
             } else if constexpr (MODE == MODE_APPLY_T2) {
                 const R M[3][3] = {{cf[0], cf[1], cf[2]}, {cf[3], cf[4], cf[5]}, {cf[6], cf[7], cf[8]}};
                 const R tau[6] = {cf[9], cf[10], cf[11], cf[12], cf[13], cf[14]};
@@ -978,7 +989,7 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
         if (active) store_slots<N>(gW, tid, Q);
         __syncthreads();
         if constexpr (SW > 0) backward_sweeps_mfma<N, HX, SW>(v_of<R>(p), bp, bm, MM, gW, vW, bW, sL);
-        else backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TR, gW, vW, bW, sL);
+        else backward_sweeps<N, HX>(v_of<R>(p), bp, bm, TW, gW, vW, bW, sL);
     }
 }
 

@@ -63,7 +63,7 @@ hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hip
                               int sweep, const LaunchTiming& tm) {
     if (p.ne <= 0) return hipSuccess;
     if (p.conn) return sweep ? hipErrorInvalidValue : launch_cell_kernel_hex(mode, t, p, stream, fp32, tm);
-    if (wave_apply(t.n, mode, false, sweep, fp32) || (p.colour > 0 && wave_apply(t.n, mode, false, sweep, true)))
+    if (wave_apply(t.n, mode, false, sweep, fp32, p.colour > 0))
         return launch_wave(mode, fp32, t, p, stream, tm);
     switch (t.n) {
         case 2: return launch_n<2, false>(mode, fp32, t, p, stream, sweep, tm);

@@ -104,9 +104,9 @@ hipError_t launch_cell_kernel(int mode, const Tables1D& t, const KParams& p, hip
 // True when launch_cell_kernel runs a tangent apply of this kind with the
 // wavefront-per-two-cells kernel (Q2 structured boxes, vector-ALU sweeps),
 // which reads the constraint bitmap and the colour of KParams itself; fp32:
-// FP32 sweeps.  Launches with a colour (the coloured mode, which only that
-// kernel has) run it whenever wave_apply(..., fp32 = true) holds.
-bool wave_apply(int n, int mode, bool hex, int sweep, bool fp32);
+// FP32 vectors; coloured: the coloured mode (p.colour > 0), which only that
+// kernel has, so every apply mode it holds runs there.
+bool wave_apply(int n, int mode, bool hex, int sweep, bool fp32, bool coloured);
 // The launch of those applies (reached through launch_cell_kernel).
 hipError_t launch_wave(int mode, bool fp32, const Tables1D& t, const KParams& p, hipStream_t stream,
                        const LaunchTiming& tm);

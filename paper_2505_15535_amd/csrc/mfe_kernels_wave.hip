@@ -5,18 +5,19 @@
 
 namespace mfe {
 
-bool wave_apply(int n, int mode, bool hex, int sweep, bool fp32) {
+bool wave_apply(int n, int mode, bool hex, int sweep, bool fp32, bool coloured) {
     if (n != 3 || hex || sweep != 0) return false;
     switch (mode) {
-        // FP64 on-the-fly with the closed form is VALU bound and runs faster
-        // with the line-per-thread brick kernel, whose 256 lanes all hold a
-        // point, than with 54 of 64 lanes per wavefront (48^3 Q2: 143 us
-        // against 174 us); the FP32 variant is faster here (139 against 158 us)
+        // the on-the-fly strategies are bound by their arithmetic and run
+        // faster with the brick kernel, whose 256 lanes all hold a point,
+        // than with 54 of 64 lanes per wavefront (48^3 Q2, FP64: OTF 120
+        // against 140 us, OTF-AD 129 against 140 us; FP32 OTF: equal); the
+        // FP32 geometry-cached one is faster here (98 against 113 us)
         case MODE_APPLY_OTF:
-        case MODE_APPLY_OTF_GEOM: return fp32;
+        case MODE_APPLY_OTF_AD: return coloured;
+        case MODE_APPLY_OTF_GEOM: return fp32 || coloured;
         case MODE_APPLY_T2:
         case MODE_APPLY_T4:
-        case MODE_APPLY_OTF_AD:
         case MODE_APPLY_OTF_AD_SPLIT: return true;
         default: return false;
     }
