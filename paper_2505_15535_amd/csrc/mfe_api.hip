@@ -309,8 +309,9 @@ struct mfe_ctx {
     double* d_energy = nullptr;  // per-brick energy partials and their sum
     double* d_partials = nullptr;
     double* h_scalars = nullptr;
-    double* d_lz = nullptr;  // eigenvalue estimate: device history of its CG coefficients
+    double* d_lz = nullptr;  // eigenvalue estimates: device history of their CG coefficients
     double* h_lz = nullptr;  // and its pinned host copy
+    size_t lz_levels = 0;    // levels the two hold
     int* d_bad = nullptr;
     // host copies used to derive coarser levels
     std::vector<double> h_verts;
@@ -848,6 +849,20 @@ int mfe_set_constraints(mfe_ctx* c, int64_t n, const int64_t* dofs) {
     c->n_con = (int64_t)idx.size();
     c->h_cidx = idx;
     mg_free(c);
+    return MFE_OK;
+}
+
+// The state update of mfe_set_state without its host wait: the det F check
+// is queued into c->d_flag, which the caller reads (and acts on) later.
+int set_state_queued(mfe_ctx* c, const double* u, hipStream_t s) {
+    MFE_HIP(c, hipMemcpyAsync(c->d_u, u, c->n_dofs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MFE_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+    KParams p = base_params(c);
+    MFE_HIP(c, mfe::launch_cell_kernel(mfe::MODE_STATE, c->tab, p, s));
+    c->state_version++;
+    c->cache_valid[1] = c->cache_valid[2] = false;
+    c->cache32_valid[1] = c->cache32_valid[2] = false;
+    c->has_state = true;
     return MFE_OK;
 }
 
@@ -1492,81 +1507,87 @@ double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) 
     return hi;
 }
 
-// Estimate of lambda_max(D^-1 K) on a level: up to 16 steps of Jacobi-
-// preconditioned CG (FP64, second-order cache) from the level's fixed random
-// right-hand side; the CG coefficients give the Lanczos tridiagonal matrix of
-// D^-1 K, whose largest eigenvalue approaches lambda_max from below.  Stops
-// once the estimate changes by less than 0.5% between steps (after 6).
-int lanczos_lmax(mfe_ctx* c, MGLevel& L, hipStream_t s, double& lmax) {
-    const int64_t n = L.ctx->n_dofs;
-    const int m = (int)std::min<int64_t>(16, n);
-    double* x = L.v64.x;
-    double* r = L.v64.b;
-    double* z = L.v64.tmp1;
-    double* pv = L.v64.d;
-    double* Ap = L.v64.r;
-    // The CG steps run with alpha and beta formed on the device; their dot
-    // products stay in a device history (hp + 2k: p.Ap of step k; hr + 2k:
-    // (r.r, r.z) before step k), which the host reads only once the stopping
-    // test can fire (after step 6, then after every step) and replays with
-    // the same arithmetic.  Steps past a stop only do discarded work.
-    constexpr int kHist = 2 * 17;
-    if (!c->d_lz) MFE_HIP(c, hipMalloc(&c->d_lz, 2 * kHist * sizeof(double)));
-    if (!c->h_lz) MFE_HIP(c, hipHostMalloc(&c->h_lz, 2 * kHist * sizeof(double), hipHostMallocDefault));
-    double* hp = c->d_lz;
-    double* hr = c->d_lz + kHist;
-    MFE_HIP(c, mfe::launch_fill(x, n, 0.0, s));
-    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, r, n, s));
-    MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, r, z, n, s));
-    MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, s));
-    MFE_HIP(c, mfe::launch_dot2(r, r, r, z, n, c->d_partials, hr, s));
-    std::vector<double> diag, off;
-    double alpha_prev = 0.0, beta_prev = 0.0;
-    const int first = std::min(5, m - 1);
-    int done = 0;
-    bool stop = false;
-    for (int k = 0; k < m && !stop; ++k) {
-        int rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
-        if (rc != MFE_OK) return L.ctx != c ? child_fail(c, L.ctx, rc, "apply") : rc;
-        MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, c->d_partials, hp + 2 * k, s));
-        MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, L.v64.dinv, hr + 2 * k + 1, hp + 2 * k, n, c->d_partials,
-                                             hr + 2 * (k + 1), s));
-        MFE_HIP(c, mfe::launch_p_update_dev(z, hr + 2 * (k + 1) + 1, hr + 2 * k + 1, pv, n, s));
-        if (k < first) continue;
-        MFE_HIP(c, hipMemcpyAsync(c->h_lz, c->d_lz, 2 * kHist * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFE_HIP(c, hipStreamSynchronize(s));
-        const double* Hp = c->h_lz;
-        const double* Hr = c->h_lz + kHist;
-        for (int j = done; j <= k && !stop; ++j) {
+// Estimates of lambda_max(D^-1 K) on several levels at once: kLanczosSteps
+// steps of Jacobi-preconditioned CG (FP64, second-order cache) from each
+// level's fixed random right-hand side; the CG coefficients give the Lanczos
+// tridiagonal matrix of D^-1 K, whose largest eigenvalue approaches
+// lambda_max from below (the smoothers use 1.2 times it).  The steps of all
+// levels are queued interleaved with alpha and beta formed on the device;
+// their dot products stay in a device history per level (hp + 2k: p.Ap of
+// step k; hr + 2k: (r.r, r.z) before step k), which the host reads once, for
+// all levels, and replays with the same arithmetic.  A level whose CG finds
+// an invariant subspace stops there (later steps only do discarded work).
+constexpr int kLanczosSteps = 8;
+constexpr int kLzHist = 2 * (kLanczosSteps + 1);
+
+int lanczos_levels(mfe_ctx* c, const std::vector<MGLevel*>& levels, hipStream_t s) {
+    const size_t nlev = levels.size();
+    if (nlev == 0) return MFE_OK;
+    if (nlev > c->lz_levels) {
+        dfree(c->d_lz);
+        if (c->h_lz) (void)hipHostFree(c->h_lz);
+        c->h_lz = nullptr;
+        c->lz_levels = 0;
+        MFE_HIP(c, hipMalloc(&c->d_lz, nlev * 2 * kLzHist * sizeof(double)));
+        MFE_HIP(c, hipHostMalloc(&c->h_lz, nlev * 2 * kLzHist * sizeof(double), hipHostMallocDefault));
+        c->lz_levels = nlev;
+    }
+    for (size_t i = 0; i < nlev; ++i) {
+        MGLevel& L = *levels[i];
+        const int64_t n = L.ctx->n_dofs;
+        double* hr = c->d_lz + i * 2 * kLzHist + kLzHist;
+        MFE_HIP(c, mfe::launch_fill(L.v64.x, n, 0.0, s));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, L.v64.b, n, s));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, L.v64.b, L.v64.tmp1, n, s));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.v64.tmp1, L.v64.d, n, s));
+        MFE_HIP(c, mfe::launch_dot2(L.v64.b, L.v64.b, L.v64.b, L.v64.tmp1, n, c->d_partials, hr, s));
+    }
+    for (int k = 0; k < kLanczosSteps; ++k) {
+        for (size_t i = 0; i < nlev; ++i) {
+            MGLevel& L = *levels[i];
+            const int64_t n = L.ctx->n_dofs;
+            if (k >= n) continue;
+            double* x = L.v64.x;
+            double* r = L.v64.b;
+            double* z = L.v64.tmp1;
+            double* pv = L.v64.d;
+            double* Ap = L.v64.r;
+            double* hp = c->d_lz + i * 2 * kLzHist;
+            double* hr = hp + kLzHist;
+            int rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
+            if (rc != MFE_OK) return L.ctx != c ? child_fail(c, L.ctx, rc, "apply") : rc;
+            MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, c->d_partials, hp + 2 * k, s));
+            MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, L.v64.dinv, hr + 2 * k + 1, hp + 2 * k, n,
+                                                 c->d_partials, hr + 2 * (k + 1), s));
+            MFE_HIP(c, mfe::launch_p_update_dev(z, hr + 2 * (k + 1) + 1, hr + 2 * k + 1, pv, n, s));
+        }
+    }
+    MFE_HIP(c, hipMemcpyAsync(c->h_lz, c->d_lz, nlev * 2 * kLzHist * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFE_HIP(c, hipStreamSynchronize(s));
+    for (size_t i = 0; i < nlev; ++i) {
+        MGLevel& L = *levels[i];
+        const int m = (int)std::min<int64_t>(kLanczosSteps, L.ctx->n_dofs);
+        const double* Hp = c->h_lz + i * 2 * kLzHist;
+        const double* Hr = Hp + kLzHist;
+        std::vector<double> diag, off;
+        double alpha_prev = 0.0, beta_prev = 0.0;
+        for (int j = 0; j < m; ++j) {
             const double rz = Hr[2 * j + 1], pAp = Hp[2 * j], rz_new = Hr[2 * (j + 1) + 1];
             if (!(pAp > 0.0) || !std::isfinite(pAp))
                 return fail(c, MFE_ENOTCONV, "eigenvalue estimate: level tangent is not positive definite");
             const double alpha = rz / pAp;
             diag.push_back(1.0 / alpha + (j > 0 ? beta_prev / alpha_prev : 0.0));
-            if (!(rz_new > 1e-30 * rz)) {  // invariant subspace found
-                stop = true;
-                break;
-            }
+            if (!(rz_new > 1e-30 * rz)) break;  // invariant subspace found
             const double beta = rz_new / rz;
-            if (j >= 5) {  // converged estimate?
-                std::vector<double> o2(off.begin(), off.end());
-                o2.resize(diag.size() - 1);
-                const double est = tridiag_lmax(diag, o2);
-                if (j > 5 && std::fabs(est - lmax) <= 0.005 * est) {
-                    stop = true;
-                    break;
-                }
-                lmax = est;
-            }
             if (j + 1 < m) off.push_back(std::sqrt(beta) / alpha);
             alpha_prev = alpha;
             beta_prev = beta;
         }
-        done = k + 1;
+        off.resize(diag.size() > 0 ? diag.size() - 1 : 0);
+        const double lmax = tridiag_lmax(diag, off);
+        if (!(lmax > 0.0) || !std::isfinite(lmax)) return fail(c, MFE_ENOTCONV, "eigenvalue estimate failed");
+        L.lmax = lmax;
     }
-    off.resize(diag.size() > 0 ? diag.size() - 1 : 0);
-    lmax = tridiag_lmax(diag, off);
-    if (!(lmax > 0.0) || !std::isfinite(lmax)) return fail(c, MFE_ENOTCONV, "eigenvalue estimate failed");
     return MFE_OK;
 }
 
@@ -1645,7 +1666,8 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
             MGLevel& F = c->mg[l - 1];
             rc = tensor_apply(c, F.I, static_cast<const double*>(F.ctx->d_u), F.v64.tmp1, F.v64.tmp2, L.v64.x, s);
             if (rc != MFE_OK) return rc;
-            rc = mfe_set_state(lc, L.v64.x, s);
+            // the coarse states' det F checks are read with the diagonals' below
+            rc = set_state_queued(lc, L.v64.x, s);
             if (rc != MFE_OK) return child_fail(c, lc, rc, "state");
         }
         if (cached) {
@@ -1661,12 +1683,26 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
         }
         rc = diagonal_into(lc, L.v64.dinv, s);
         if (rc != MFE_OK) return l ? child_fail(c, lc, rc, "diagonal") : rc;
-        MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
-        MFE_HIP(c, mfe::launch_invert(L.v64.dinv, lc->n_dofs, c->d_bad, s));
-        int bad = 0;
-        MFE_HIP(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        if (l == 0) MFE_HIP(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), s));
+        MFE_HIP(c, mfe::launch_invert(L.v64.dinv, lc->n_dofs, c->d_bad, s));  // every level flags into d_bad
+    }
+    {
+        // one host wait for every level: the coarse states' det F flags, then
+        // the diagonals' flag
+        const size_t nlv = c->mg.size();
+        std::vector<int> flags(nlv + 1, 0);
+        for (size_t l = 1; l < nlv; ++l)
+            MFE_HIP(c, hipMemcpyAsync(&flags[l], c->mg[l].ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        MFE_HIP(c, hipMemcpyAsync(&flags[nlv], c->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
         MFE_HIP(c, hipStreamSynchronize(s));
-        if (bad) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
+        for (size_t l = 1; l < nlv; ++l)
+            if (flags[l]) {
+                mfe_ctx* lc = c->mg[l].ctx;
+                lc->has_state = false;
+                fail(lc, MFE_EJACOBIAN, "det F <= 0 at some quadrature point");
+                return child_fail(c, lc, MFE_EJACOBIAN, "state");
+            }
+        if (flags[nlv]) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
     }
     // The coarsest level's direct-solve set-up (one workgroup, ~0.6 ms) runs
     // on the side stream while the other levels' eigenvalue estimates run on
@@ -1696,23 +1732,30 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
             MFE_HIP(c, hipEventRecord(c->side_join, c->side_stream));
         }
     }
+    {
+        // spectrum estimates of the smoothed levels, all at once (the
+        // coarsest one too unless its direct solve is being set up)
+        std::vector<MGLevel*> est;
+        for (size_t l = 0; l + 1 < nl; ++l) est.push_back(&c->mg[l]);
+        if (!dense) est.push_back(&Lc);
+        int rc = lanczos_levels(c, est, s);
+        if (rc != MFE_OK) return rc;
+        if (dense) {
+            MFE_HIP(c, hipStreamWaitEvent(s, c->side_join, 0));
+            rc = dense_finish(c, Lc, fp32, s, Lc.dense_ok);
+            if (rc != MFE_OK) return rc;
+            guard.side = nullptr;  // joined: dense_finish waited for it
+            if (Lc.dense_ok) {
+                Lc.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
+            } else {
+                rc = lanczos_levels(c, std::vector<MGLevel*>{&Lc}, s);
+                if (rc != MFE_OK) return rc;
+            }
+        }
+    }
     for (size_t l = 0; l < nl; ++l) {
         MGLevel& L = c->mg[l];
         mfe_ctx* lc = L.ctx;
-        if (l + 1 == nl && dense) {
-            MFE_HIP(c, hipStreamWaitEvent(s, c->side_join, 0));
-            const int rc = dense_finish(c, L, fp32, s, L.dense_ok);
-            if (rc != MFE_OK) return rc;
-            guard.side = nullptr;  // joined: dense_finish waited for it
-        }
-        if (L.dense_ok) {
-            L.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
-        } else {
-            double lam = 0.0;
-            const int rc = lanczos_lmax(c, L, s, lam);
-            if (rc != MFE_OK) return rc;
-            L.lmax = lam;
-        }
         // the V-cycle works on the free dofs: the smoother never moves a
         // constrained entry, and its operator-output buffer starts cleared
         if (lc->n_con > 0) MFE_HIP(c, mfe::launch_set_indexed(lc->d_cidx, lc->n_con, 0.0, L.v64.dinv, s));
@@ -2571,6 +2614,7 @@ int mfe_set_network(mfe_ctx* c, const float* params_host, int variant) {
     if (variant != MFE_NET_RELU && variant != MFE_NET_LINEAR) return fail(c, MFE_EINVAL, "unknown network variant");
     c->net_variant = variant;
     c->net_off = false;
+    c->mg_graph_valid = false;  // a captured cycle holds the parameter pointer and the variant
     DeviceGuard g(c->device);
     if (!params_host) {
         dfree(c->d_net);

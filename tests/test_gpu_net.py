@@ -178,6 +178,14 @@ def test_learned_step_in_the_smoother(torch_dev):
         z_plain = op.gmg_apply(r, **o)
         rows.append((energy(e, z_stop, r), energy(e, z_net, r), energy(e, z_plain, r)))
     rows = np.array(rows)
+    # a new network (cleared, then set again with the other variant) is what the next cycle uses
+    op.set_network(None)
+    op.set_network(netw.params(), "linear")
+    z_lin = op.gmg_apply(rs[0], net=True, **o)
+    z_lin0 = op.gmg_apply(rs[0], net=True, mg_graph=0, **o)
+    assert float(torch.linalg.norm(z_lin - z_lin0) / torch.linalg.norm(z_lin0)) < 1e-10
+    assert float(torch.linalg.norm(z_lin - z_net) / torch.linalg.norm(z_net)) > 1e-8
+    op.set_network(netw.params())
     print("error energy after the cycle: stopped before the step / with the learned step / plain\n", rows.round(4))
     assert np.all(rows[:, 1] <= rows[:, 0] * (1.0 + 1e-9))
     assert rows[:, 1].mean() < rows[:, 2].mean()
