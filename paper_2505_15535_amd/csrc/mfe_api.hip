@@ -312,6 +312,10 @@ struct mfe_ctx {
     double* d_lz = nullptr;  // eigenvalue estimates: device history of their CG coefficients
     double* h_lz = nullptr;  // and its pinned host copy
     size_t lz_levels = 0;    // levels the two hold
+    double* d_lz_part = nullptr;         // per-level partial sums of their dot products
+    std::vector<hipStream_t> lz_streams;  // one stream per level for them (default priority)
+    std::vector<hipEvent_t> lz_join;
+    hipEvent_t lz_fork = nullptr;
     int* d_bad = nullptr;
     // host copies used to derive coarser levels
     std::vector<double> h_verts;
@@ -593,6 +597,10 @@ void mfe_destroy(mfe_ctx* c) {
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     if (c->side_fork) (void)hipEventDestroy(c->side_fork);
     if (c->side_join) (void)hipEventDestroy(c->side_join);
+    for (auto st : c->lz_streams) (void)hipStreamDestroy(st);
+    for (auto e : c->lz_join) (void)hipEventDestroy(e);
+    if (c->lz_fork) (void)hipEventDestroy(c->lz_fork);
+    dfree(c->d_lz_part);
     if (c->d_bad_dense) (void)hipFree(c->d_bad_dense);
     delete c;
 }
@@ -1511,12 +1519,13 @@ double tridiag_lmax(const std::vector<double>& a, const std::vector<double>& b) 
 // steps of Jacobi-preconditioned CG (FP64, second-order cache) from each
 // level's fixed random right-hand side; the CG coefficients give the Lanczos
 // tridiagonal matrix of D^-1 K, whose largest eigenvalue approaches
-// lambda_max from below (the smoothers use 1.2 times it).  The steps of all
-// levels are queued interleaved with alpha and beta formed on the device;
-// their dot products stay in a device history per level (hp + 2k: p.Ap of
-// step k; hr + 2k: (r.r, r.z) before step k), which the host reads once, for
-// all levels, and replays with the same arithmetic.  A level whose CG finds
-// an invariant subspace stops there (later steps only do discarded work).
+// lambda_max from below (the smoothers use 1.2 times it).  Each level's
+// steps run on a stream of its own (the levels are independent, and their
+// short kernels overlap), with alpha and beta formed on the device; the dot
+// products stay in a device history per level (hp + 2k: p.Ap of step k;
+// hr + 2k: (r.r, r.z) before step k), which the host reads once, for all
+// levels, and replays with the same arithmetic.  A level whose CG finds an
+// invariant subspace stops there (later steps only do discarded work).
 constexpr int kLanczosSteps = 8;
 constexpr int kLzHist = 2 * (kLanczosSteps + 1);
 
@@ -1525,42 +1534,63 @@ int lanczos_levels(mfe_ctx* c, const std::vector<MGLevel*>& levels, hipStream_t 
     if (nlev == 0) return MFE_OK;
     if (nlev > c->lz_levels) {
         dfree(c->d_lz);
+        dfree(c->d_lz_part);
         if (c->h_lz) (void)hipHostFree(c->h_lz);
         c->h_lz = nullptr;
         c->lz_levels = 0;
         MFE_HIP(c, hipMalloc(&c->d_lz, nlev * 2 * kLzHist * sizeof(double)));
+        MFE_HIP(c, hipMalloc(&c->d_lz_part, nlev * 2 * mfe::kDotBlocks * sizeof(double)));
         MFE_HIP(c, hipHostMalloc(&c->h_lz, nlev * 2 * kLzHist * sizeof(double), hipHostMallocDefault));
         c->lz_levels = nlev;
     }
+    while (c->lz_streams.size() < nlev) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        MFE_HIP(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->lz_streams.push_back(st);
+        MFE_HIP(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->lz_join.push_back(ev);
+    }
+    if (!c->lz_fork) MFE_HIP(c, hipEventCreateWithFlags(&c->lz_fork, hipEventDisableTiming));
+    // the levels are independent: each runs its steps on a stream of its own
+    // (forked from s, joined back into s), with its own partial-sum scratch
+    struct Join {
+        mfe_ctx* c;
+        size_t n = 0;
+        ~Join() {  // an early return leaves no level work behind
+            for (size_t i = 0; i < n; ++i) (void)hipStreamSynchronize(c->lz_streams[i]);
+        }
+    } join{c};
+    MFE_HIP(c, hipEventRecord(c->lz_fork, s));
     for (size_t i = 0; i < nlev; ++i) {
         MGLevel& L = *levels[i];
+        const hipStream_t ls = c->lz_streams[i];
+        MFE_HIP(c, hipStreamWaitEvent(ls, c->lz_fork, 0));
+        join.n = i + 1;
         const int64_t n = L.ctx->n_dofs;
-        double* hr = c->d_lz + i * 2 * kLzHist + kLzHist;
-        MFE_HIP(c, mfe::launch_fill(L.v64.x, n, 0.0, s));
-        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, L.v64.b, n, s));
-        MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, L.v64.b, L.v64.tmp1, n, s));
-        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.v64.tmp1, L.v64.d, n, s));
-        MFE_HIP(c, mfe::launch_dot2(L.v64.b, L.v64.b, L.v64.b, L.v64.tmp1, n, c->d_partials, hr, s));
-    }
-    for (int k = 0; k < kLanczosSteps; ++k) {
-        for (size_t i = 0; i < nlev; ++i) {
-            MGLevel& L = *levels[i];
-            const int64_t n = L.ctx->n_dofs;
-            if (k >= n) continue;
-            double* x = L.v64.x;
-            double* r = L.v64.b;
-            double* z = L.v64.tmp1;
-            double* pv = L.v64.d;
-            double* Ap = L.v64.r;
-            double* hp = c->d_lz + i * 2 * kLzHist;
-            double* hr = hp + kLzHist;
-            int rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, s);
+        double* part = c->d_lz_part + i * 2 * mfe::kDotBlocks;
+        double* x = L.v64.x;
+        double* r = L.v64.b;
+        double* z = L.v64.tmp1;
+        double* pv = L.v64.d;
+        double* Ap = L.v64.r;
+        double* hp = c->d_lz + i * 2 * kLzHist;
+        double* hr = hp + kLzHist;
+        MFE_HIP(c, mfe::launch_fill(x, n, 0.0, ls));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, L.rnd, r, n, ls));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, L.v64.dinv, r, z, n, ls));
+        MFE_HIP(c, mfe::launch_scale_mul(1.0, nullptr, z, pv, n, ls));
+        MFE_HIP(c, mfe::launch_dot2(r, r, r, z, n, part, hr, ls));
+        for (int k = 0; k < kLanczosSteps && k < n; ++k) {
+            int rc = mfe_apply_tangent(L.ctx, pv, Ap, MFE_T2, MFE_FP64, ls);
             if (rc != MFE_OK) return L.ctx != c ? child_fail(c, L.ctx, rc, "apply") : rc;
-            MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, c->d_partials, hp + 2 * k, s));
-            MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, L.v64.dinv, hr + 2 * k + 1, hp + 2 * k, n,
-                                                 c->d_partials, hr + 2 * (k + 1), s));
-            MFE_HIP(c, mfe::launch_p_update_dev(z, hr + 2 * (k + 1) + 1, hr + 2 * k + 1, pv, n, s));
+            MFE_HIP(c, mfe::launch_dot2(pv, Ap, nullptr, nullptr, n, part, hp + 2 * k, ls));
+            MFE_HIP(c, mfe::launch_cg_update_dev(x, r, z, pv, Ap, L.v64.dinv, hr + 2 * k + 1, hp + 2 * k, n, part,
+                                                 hr + 2 * (k + 1), ls));
+            MFE_HIP(c, mfe::launch_p_update_dev(z, hr + 2 * (k + 1) + 1, hr + 2 * k + 1, pv, n, ls));
         }
+        MFE_HIP(c, hipEventRecord(c->lz_join[i], ls));
+        MFE_HIP(c, hipStreamWaitEvent(s, c->lz_join[i], 0));
     }
     MFE_HIP(c, hipMemcpyAsync(c->h_lz, c->d_lz, nlev * 2 * kLzHist * sizeof(double), hipMemcpyDeviceToHost, s));
     MFE_HIP(c, hipStreamSynchronize(s));
