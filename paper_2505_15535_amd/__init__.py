@@ -383,6 +383,24 @@ def _dev_f64(t, n, name):
     return _dev_tensor(t, n, name, torch.float64)
 
 
+def save_checkpoint(path, u, prev, t, h, h_cap, prev_h, n_steps):
+    """State of the load-path driver after a converged step, as an .npz file
+    (written to a temporary name and renamed, so an interruption leaves the
+    previous checkpoint intact)."""
+    import numpy as np
+    tmp = str(path) + ".tmp.npz"
+    np.savez(tmp, u=u.detach().cpu().numpy(), prev=prev.detach().cpu().numpy(), t=float(t), h=float(h),
+             h_cap=float(h_cap), prev_h=float("nan") if prev_h is None else float(prev_h), n_steps=int(n_steps))
+    os.replace(tmp, str(path))
+
+
+def load_checkpoint(path):
+    """The arrays saved by save_checkpoint (no pickled objects are loaded)."""
+    import numpy as np
+    with np.load(str(path), allow_pickle=False) as f:
+        return {k: f[k] for k in f.files}
+
+
 class Operator:
     """A context holding one mesh, material, constraints, state and caches.
 
@@ -621,7 +639,7 @@ class Operator:
         return v
 
     def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, on_step=None,
-                        extrapolate=True, **opts):
+                        extrapolate=True, checkpoint=None, resume=False, **opts):
         """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping).
 
         boundary_values(t) -> (dofs, values): prescribed values at load t on the
@@ -634,6 +652,11 @@ class Operator:
         converged states (extrapolate=True) or from the last converged state.
         u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
         on_step(t, u), if given, is called after every converged step.
+        checkpoint: path of an .npz file rewritten after every converged step
+        with everything the driver needs to go on (state, previous state, t,
+        next increment and its limits); resume=True starts from that file
+        instead of t = 0 (u is overwritten with its state), so a resumed path
+        takes the same steps as an uninterrupted one.
         Returns a list of per-step reports (dicts with t, h and the solver report).
         """
         import numpy as np
@@ -645,6 +668,14 @@ class Operator:
         t, h0 = 0.0, 1.0 / n_steps
         h = h0
         h_cap = h0
+        if resume:
+            ck = load_checkpoint(checkpoint)
+            if int(ck["n_steps"]) != n_steps or ck["u"].size != n:
+                raise ValueError("checkpoint is of another path or mesh")
+            u.copy_(torch.from_numpy(ck["u"]))
+            prev.copy_(torch.from_numpy(ck["prev"]))
+            t, h, h_cap = float(ck["t"]), float(ck["h"]), float(ck["h_cap"])
+            prev_h = None if np.isnan(ck["prev_h"]) else float(ck["prev_h"])
         reports = []
         while t < 1.0 - 1e-12:
             h = min(h, 1.0 - t)
@@ -669,9 +700,12 @@ class Operator:
                 prev_h = h
                 t += h
                 reports.append(dict(t=t, h=h, **rep))
+                h = min(h_cap, 1.25 * h)
+                if checkpoint is not None:
+                    save_checkpoint(checkpoint, u=u, prev=prev, t=t, h=h, h_cap=h_cap, prev_h=prev_h,
+                                    n_steps=n_steps)
                 if on_step is not None:
                     on_step(t, u)
-                h = min(h_cap, 1.25 * h)
             else:
                 reports.append(dict(t=t + h, h=h, failed=True, **rep))
                 h_cap = min(h_cap, 0.9 * h)

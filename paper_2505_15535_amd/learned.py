@@ -95,6 +95,30 @@ class Net:
     def params(self) -> np.ndarray:
         return self.w.cpu().numpy().copy()
 
+    def save(self, path, **extra):
+        """Parameters, Adam moments and step count (and any `extra` arrays) as
+        an .npz file, written whole or not at all, so that training resumed
+        from it takes the same steps as uninterrupted."""
+        import os
+        tmp = str(path) + ".tmp.npz"
+        np.savez(tmp, w=self.params(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(), step=self.step,
+                 variant=self.variant, **extra)
+        os.replace(tmp, path)
+
+    @classmethod
+    def load(cls, path, device):
+        with np.load(path, allow_pickle=False) as f:
+            net = cls(f["w"], device, str(f["variant"]))
+            net.m.copy_(torch_from(f["m"], device))
+            net.v.copy_(torch_from(f["v"], device))
+            net.step = int(f["step"])
+        return net
+
+
+def torch_from(a, device):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
 
 def beam(nx, ny, nz, lam, device=0):
     """Operator of the twisted beam (clamped at x = 0) and its boundary data function."""
@@ -209,18 +233,32 @@ def energy_step(op, net, r1, lr=None):
     return J
 
 
-def train(data, nx=64, ny=16, nz=16, epochs=10, lr=1e-3, seed=0, device=0, log=None, variant="relu"):
+def train(data, nx=64, ny=16, nz=16, epochs=10, lr=1e-3, seed=0, device=0, log=None, variant="relu",
+          checkpoint=None, resume=False):
     """Adam on the energy of the correction over every (state, residual) of
-    `data` (from generate); returns (Net, per-epoch mean J)."""
+    `data` (from generate); returns (Net, per-epoch mean J).
+    checkpoint: path of an .npz file rewritten after every epoch with the
+    network, its Adam moments, the epoch count, the shuffling generator's
+    state and the loss history; resume=True goes on from that file."""
+    import json
     import torch
-    net = Net(init_params(seed), torch.device("cuda", device), variant)
+    dev = torch.device("cuda", device)
     rng = np.random.default_rng(seed)
     hist = []
+    first = 0
+    if not resume:
+        net = Net(init_params(seed), dev, variant)
+    else:
+        net = Net.load(checkpoint, dev)
+        with np.load(checkpoint, allow_pickle=False) as f:
+            first = int(f["epoch"])
+            rng.bit_generator.state = json.loads(str(f["rng"]))
+            hist = [float(x) for x in f["hist"]]
     ops = {}
     for lam, _ in data:
         if lam not in ops:
             ops[lam] = beam(nx, ny, nz, lam, device)
-    for ep in range(epochs):
+    for ep in range(first, epochs):
         tot, cnt = 0.0, 0
         order = [(li, si) for li, (_, ss) in enumerate(data) for si in range(len(ss))]
         rng.shuffle(order)
@@ -236,6 +274,8 @@ def train(data, nx=64, ny=16, nz=16, epochs=10, lr=1e-3, seed=0, device=0, log=N
         hist.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep}: mean J {hist[-1]:.4e}")
+        if checkpoint is not None:
+            net.save(checkpoint, epoch=ep + 1, rng=json.dumps(rng.bit_generator.state), hist=np.asarray(hist))
     for op, _, _ in ops.values():
         op.close()
     return net, hist

@@ -85,6 +85,31 @@ def test_adam_parity(torch_dev):
     assert _rel(W.cpu().numpy() - w, wr - w) <= 1e-4
 
 
+
+def test_training_resumes_from_checkpoint(torch_dev, tmp_path):
+    """Adam training stopped after two steps, saved, loaded into a new network
+    and continued gives bitwise the parameters and moments of the
+    uninterrupted run (the forward, loss, backward and Adam kernels reduce in
+    a fixed order)."""
+    from paper_2505_15535_amd import learned
+    torch, dev = torch_dev
+    rng = np.random.default_rng(3)
+    P = 4
+    batches = [(torch.from_numpy(rng.normal(size=(P, 6, 729)).astype(np.float32)).to(dev),
+                torch.from_numpy(rng.normal(size=(P, 3, 729)).astype(np.float32)).to(dev)) for _ in range(4)]
+    a = learned.Net(learned.init_params(5), dev, "relu")
+    path = tmp_path / "net.npz"
+    losses = []
+    for k, (x, t) in enumerate(batches):
+        losses.append(a.train_step(x, t, 1e-3))
+        if k == 1:
+            a.save(path)
+    b = learned.Net.load(path, dev)
+    assert b.step == 2
+    resumed = [b.train_step(x, t, 1e-3) for x, t in batches[2:]]
+    assert resumed == losses[2:]
+    assert torch.equal(a.w, b.w) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v) and a.step == b.step
+
 def test_patch_gather_scatter_and_invariants(torch_dev):
     import paper_2505_15535_amd as mfe
     torch, dev = torch_dev

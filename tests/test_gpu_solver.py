@@ -365,3 +365,62 @@ def test_gmg_direct_coarse_falls_back_on_indefinite_level(torch_dev):
     z = op.gmg_apply(_to(torch_dev, r), **opts).cpu().numpy()
     ref = spla.spsolve(P.assemble_tangent(u_ok).tocsc(), r)
     assert np.linalg.norm(z - ref) / np.linalg.norm(ref) <= 1e-10
+
+
+def test_load_path_resumes_from_checkpoint(torch_dev, tmp_path):
+    """A load path stopped after its second step and resumed from the
+    checkpoint file takes the same remaining steps as the uninterrupted path
+    and ends at the same state (to the Newton tolerance)."""
+    import shutil
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz, L, lam = 8, 2, 2, (4.0, 1.0, 1.0), 100.0
+    verts = synthetic.box_vertices(nx, ny, nz, L)
+    cdofs, _ = synthetic.clamp_and_twist(nx, ny, nz, 2, L, 0.0)
+    # 4 degrees a step keeps every Newton solve in its quadratic phase; in a
+    # damped phase (larger steps) the line search amplifies the rounding of
+    # the atomic sums and two runs drift apart after a few iterations
+    theta = np.deg2rad(16.0)
+    bv = lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t)
+    opts = dict(strategy="t2", preconditioner="jacobi", max_newton=30, max_cg=20000, newton_atol=1e-10,
+                cg_rtol=1e-8)
+    ck, ck2 = tmp_path / "path.npz", tmp_path / "after2.npz"
+
+    def keep_second(t, uu):
+        if abs(t - 0.5) < 1e-12:
+            shutil.copy(ck, ck2)
+
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+    op.set_constraints(cdofs)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
+    full = op.solve_load_path(u, bv, 4, on_step=keep_second, checkpoint=ck, **opts)
+    op.close()
+    assert ck2.exists()
+    assert float(mfe.load_checkpoint(ck)["t"]) == pytest.approx(1.0)
+
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+    op.set_constraints(cdofs)
+    u2 = torch.full((op.n_dofs,), np.nan, dtype=torch.float64, device=dev)   # overwritten by the checkpoint
+    rest = op.solve_load_path(u2, bv, 4, checkpoint=ck2, resume=True, **opts)
+    op.close()
+    later = [r for r in full if r["t"] > 0.5 + 1e-12]
+    assert [(r["t"], r["h"], bool(r.get("failed"))) for r in rest] == \
+        [(r["t"], r["h"], bool(r.get("failed"))) for r in later]
+    # the residual histories agree while they are above the rounding floor
+    # (the scatter's atomic sums make the last iterations, near 1e-10, vary
+    # from run to run); the next step starts from the same extrapolated state
+    for a, b in zip(rest, later):
+        ha = [x for x in a["residual_history"] if x > 1e-7]
+        hb = [x for x in b["residual_history"] if x > 1e-7]
+        assert len(ha) == len(hb), (a, b)
+        assert ha == pytest.approx(hb, rel=1e-3), (a, b)
+        assert abs(a["newton_iterations"] - b["newton_iterations"]) <= 1, (a, b)
+    assert rest[0]["residual_history"][0] == pytest.approx(later[0]["residual_history"][0], rel=1e-10)
+    a, b = u.cpu().numpy(), u2.cpu().numpy()
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) <= 1e-8
+    with pytest.raises(ValueError):
+        op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+        try:
+            op.solve_load_path(u2, bv, 3, checkpoint=ck2, resume=True, **opts)
+        finally:
+            op.close()
