@@ -375,6 +375,62 @@ typedef struct mfe_solve_report {
 int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, const double* g_dev,
                      mfe_solve_report* report, void* stream);
 
+/* Load stepping (Sec. 2.2; the twisted-beam runs of Sec. 3.1 follow a load
+ * path t in (0, 1] in steps).
+ *
+ * Position of the driver on the path.  t: load reached by the state;
+ * h: next increment (<= 0: 1 / n_steps); h_cap: largest increment allowed
+ * from now on (<= 0: 1 / n_steps); prev_h: increment that led to t (<= 0:
+ * none, so no extrapolation). */
+typedef struct mfe_path_state {
+    double t, h, h_cap, prev_h;
+} mfe_path_state;
+
+/* One Newton solve the driver attempted: the load it aimed at, its increment,
+ * failed = 1 when the attempt did not converge (then retried or halved),
+ * status = the mfe_newton_solve return code, and its report. */
+typedef struct mfe_path_report {
+    double t, h;
+    int failed, status;
+    mfe_solve_report solve;
+} mfe_path_report;
+
+/* Prescribed values at load t: fill values_host[n] (n = number of
+ * constrained dofs, in ascending dof order) and return 0; a nonzero return
+ * ends the path with MFE_EINVAL. */
+typedef int (*mfe_load_fn)(double t, double* values_host, int64_t n, void* user);
+
+/* Called after every converged step, with the stream synchronised: the new
+ * position, the state u_dev at state->t and the state before it, prev_dev
+ * (device arrays of n_dofs doubles, valid during the call).  A nonzero return
+ * stops the path there (the driver then returns MFE_OK with state->t < 1). */
+typedef int (*mfe_step_fn)(const mfe_path_state* state, const double* u_dev, const double* prev_dev, void* user);
+
+/* Follow the load path from state->t to t = 1 with mfe_newton_solve.
+ * u_dev (device, n_dofs doubles) holds the converged state at state->t on
+ * entry and at the last converged load on return; prev_dev (device, n_dofs
+ * doubles) holds the converged state before it when state->prev_h > 0 and is
+ * kept up to date (needed only with extrapolate; may be NULL otherwise).
+ * state (in/out) may be NULL: start at t = 0 with steps of 1 / n_steps.
+ * Each step aims at t + h (at most 1), takes the values load(t + h), and
+ * starts Newton from the linear extrapolation u + (h / prev_h) (u - prev)
+ * when extrapolate != 0 and a previous step exists, else from u.  An
+ * extrapolated start that does not converge is retried once from u; a step
+ * that still fails sets h_cap = min(h_cap, 0.9 h) and halves h, down to
+ * min_fraction.  After a converged step h grows to min(h_cap, 1.25 h).
+ * reports (host, may be NULL) receives up to max_reports attempts in order;
+ * *n_reports (may be NULL) their count.  The driver's two work vectors are
+ * allocated with the context's other solver vectors.  Synchronises the
+ * stream.  Returns MFE_OK at t = 1 (or when on_step stopped it), MFE_ENOTCONV
+ * when the increment falls below min_fraction (state keeps the last converged
+ * position), MFE_EINVAL for bad arguments or a failed load callback, and the
+ * error of a Newton solve that fails for a reason other than convergence
+ * (device errors, unsupported options). */
+int mfe_solve_load_path(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, double* prev_dev, int n_steps,
+                        double min_fraction, int extrapolate, mfe_path_state* state, mfe_load_fn load,
+                        void* load_user, mfe_step_fn on_step, void* step_user, mfe_path_report* reports,
+                        int max_reports, int* n_reports, void* stream);
+
 /* x = K(u)^-1 b by (preconditioned) CG at the current state, starting from
  * x = 0; b_dev, x_dev device arrays of n_dofs doubles (b must vanish at
  * constrained dofs).  Uses opts->strategy, preconditioner, max_cg, cg_rtol.
@@ -385,7 +441,7 @@ int mfe_newton_solve(mfe_ctx* ctx, const mfe_solve_opts* opts, double* u_dev, co
  * 1D transfer matrices, 8 vectors per level) is built by the first such solve
  * and kept until the mesh, material or constraints change; every solve then
  * interpolates the state to the coarser levels, builds their caches and
- * inverse diagonals, and estimates lambda_max(D^-1 K) per level from 16
+ * inverse diagonals, and estimates lambda_max(D^-1 K) per level from 8
  * Lanczos steps (Jacobi-CG on a fixed random right-hand side); the smoothers
  * use 1.2 times that estimate.  The V-cycle acts on the free dofs (the
  * smoother never moves a constrained entry) and the preconditioner is the

@@ -72,6 +72,19 @@ class SolveReport(ctypes.Structure):
                 "final_residual": self.final_residual, "residual_history": list(self.residual_history[:n])}
 
 
+class PathState(ctypes.Structure):
+    """struct mfe_path_state"""
+    _fields_ = [("t", _d), ("h", _d), ("h_cap", _d), ("prev_h", _d)]
+
+
+class PathReport(ctypes.Structure):
+    """struct mfe_path_report"""
+    _fields_ = [("t", _d), ("h", _d), ("failed", _i), ("status", _i), ("solve", SolveReport)]
+
+
+LOAD_FN = ctypes.CFUNCTYPE(_i, _d, ctypes.POINTER(_d), _i64, _vp)
+STEP_FN = ctypes.CFUNCTYPE(_i, ctypes.POINTER(PathState), _vp, _vp, _vp)
+
 _SIGS = {
     "mfe_create": (_i, [ctypes.POINTER(_vp), _i]),
     "mfe_destroy": (None, [_vp]),
@@ -98,6 +111,9 @@ _SIGS = {
     "mfe_set_deterministic": (_i, [_vp, _i]),
     "mfe_newton_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(SolveReport), _vp]),
     "mfe_cg_solve": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d), _vp]),
+    "mfe_solve_load_path": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _i, _d, _i, ctypes.POINTER(PathState),
+                                 LOAD_FN, _vp, STEP_FN, _vp, ctypes.POINTER(PathReport), _i, ctypes.POINTER(_i),
+                                 _vp]),
     "mfe_diagonal": (_i, [_vp, _vp, _vp]),
     "mfe_gmg_setup": (_i, [_vp, ctypes.POINTER(SolveOpts), _vp]),
     "mfe_set_network": (_i, [_vp, _vp, _i]),
@@ -248,6 +264,47 @@ def mfe_newton_solve(ctx, opts: SolveOpts, u_dev_ptr, g_dev_ptr=None, stream=Non
     if rc not in (MFE_OK, MFE_ENOTCONV):
         raise MfeError(rc, mfe_last_error(ctx))
     return rc, rep
+
+
+def mfe_solve_load_path(ctx, opts: SolveOpts, u_dev_ptr, prev_dev_ptr, n_steps, min_fraction, extrapolate,
+                        state: PathState, load, on_step=None, max_reports=4096, stream=None):
+    """Run the library's load-path driver.  load(t) -> values at the
+    constrained dofs (ascending dof order); on_step(state, u_ptr, prev_ptr)
+    -> truthy to stop.  Exceptions raised in the callbacks stop the path and
+    are raised again here.  Returns (status, [PathReport]); raises MfeError
+    unless the status is MFE_OK or MFE_ENOTCONV."""
+    import numpy as np
+    caught = []
+
+    def _load(t, values, n, user):
+        try:
+            vals = np.asarray(load(t), dtype=np.float64).reshape(-1)
+            if vals.size != n:
+                raise ValueError(f"load callback returned {vals.size} values for {n} constrained dofs")
+            ctypes.memmove(values, vals.ctypes.data, n * 8)
+            return 0
+        except BaseException as e:  # noqa: BLE001 -- re-raised after the C call returns
+            caught.append(e)
+            return 1
+
+    def _step(st, u_ptr, prev_ptr, user):
+        try:
+            return 1 if (on_step is not None and on_step(st.contents, u_ptr, prev_ptr)) else 0
+        except BaseException as e:  # noqa: BLE001
+            caught.append(e)
+            return 1
+
+    load_cb, step_cb = LOAD_FN(_load), STEP_FN(_step)
+    reports = (PathReport * max_reports)()
+    n_rep = _i(0)
+    rc = _lib.mfe_solve_load_path(ctx, ctypes.byref(opts), u_dev_ptr, prev_dev_ptr, int(n_steps),
+                                  float(min_fraction), int(bool(extrapolate)), ctypes.byref(state), load_cb,
+                                  None, step_cb, None, reports, max_reports, ctypes.byref(n_rep), stream)
+    if caught:
+        raise caught[0]
+    if rc not in (MFE_OK, MFE_ENOTCONV):
+        raise MfeError(rc, mfe_last_error(ctx))
+    return rc, list(reports[:n_rep.value])
 
 
 def mfe_gmg_setup(ctx, opts: SolveOpts, stream=None):
@@ -482,6 +539,7 @@ class Operator:
         import numpy as np
         d = np.ascontiguousarray(np.asarray(dofs, dtype=np.int64).reshape(-1))
         mfe_set_constraints(self.ctx, d.size, d.ctypes.data if d.size else None)
+        self._cidx = np.unique(d)   # the library's order of the constrained dofs
 
     def set_state(self, u, stream=None):
         mfe_set_state(self.ctx, _dev_f64(u, self.n_dofs, "u"), _stream_handle(stream))
@@ -639,17 +697,19 @@ class Operator:
         return v
 
     def solve_load_path(self, u, boundary_values, n_steps, min_fraction=1.0 / 256, on_step=None,
-                        extrapolate=True, checkpoint=None, resume=False, **opts):
-        """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping).
+                        extrapolate=True, checkpoint=None, resume=False, stream=None, **opts):
+        """Follow a load path t in (0, 1] with Newton-CG (Sec. 2.2, load stepping)
+        through the library's driver (mfe_solve_load_path).
 
         boundary_values(t) -> (dofs, values): prescribed values at load t on the
-        constrained dofs.  Steps of 1/n_steps; a step whose Newton solve fails is
-        retried from the last converged state instead of the extrapolated one,
-        then with half the increment (down to min_fraction), and later steps
-        stay below 0.9 times the smallest increment that failed; the increment
-        grows again by 1.25x after each converged step (up to those limits);
-        each step starts from the linear extrapolation of the two previous
-        converged states (extrapolate=True) or from the last converged state.
+        constrained dofs (constrained dofs it leaves out get 0).  Steps of
+        1/n_steps; a step whose Newton solve fails is retried from the last
+        converged state instead of the extrapolated one, then with half the
+        increment (down to min_fraction), and later steps stay below 0.9 times
+        the smallest increment that failed; the increment grows again by 1.25x
+        after each converged step (up to those limits); each step starts from
+        the linear extrapolation of the two previous converged states
+        (extrapolate=True) or from the last converged state.
         u (device tensor) holds the state at t = 0 on entry and at t = 1 on return.
         on_step(t, u), if given, is called after every converged step.
         checkpoint: path of an .npz file rewritten after every converged step
@@ -657,62 +717,53 @@ class Operator:
         next increment and its limits); resume=True starts from that file
         instead of t = 0 (u is overwritten with its state), so a resumed path
         takes the same steps as an uninterrupted one.
-        Returns a list of per-step reports (dicts with t, h and the solver report).
+        Returns a list of per-attempt reports (dicts with t, h, failed for the
+        attempts that did not converge, and the Newton report); raises
+        MfeError(MFE_ENOTCONV) when the increment falls below min_fraction.
         """
         import numpy as np
         import torch
         n = self.n_dofs
+        _dev_f64(u, n, "u")
         prev = u.clone()
-        prev_h = None
-        g = torch.zeros(n, dtype=torch.float64, device=u.device)
-        t, h0 = 0.0, 1.0 / n_steps
-        h = h0
-        h_cap = h0
+        st = PathState(0.0, 0.0, 0.0, 0.0)
         if resume:
             ck = load_checkpoint(checkpoint)
             if int(ck["n_steps"]) != n_steps or ck["u"].size != n:
                 raise ValueError("checkpoint is of another path or mesh")
             u.copy_(torch.from_numpy(ck["u"]))
             prev.copy_(torch.from_numpy(ck["prev"]))
-            t, h, h_cap = float(ck["t"]), float(ck["h"]), float(ck["h_cap"])
-            prev_h = None if np.isnan(ck["prev_h"]) else float(ck["prev_h"])
-        reports = []
-        while t < 1.0 - 1e-12:
-            h = min(h, 1.0 - t)
-            dofs, vals = boundary_values(t + h)
-            gh = np.zeros(n)
-            gh[np.asarray(dofs)] = vals
-            g.copy_(torch.from_numpy(gh))
-            trial = u.clone()
-            if extrapolate and prev_h is not None:  # trial = u + (h / prev_h) (u - prev)
-                self.axpby(1.0 + h / prev_h, u, 0.0, trial)
-                self.axpby(-h / prev_h, prev, 1.0, trial)
-            rep = self.newton_solve(trial, g=g, **opts)
-            if not rep["converged"] and extrapolate and prev_h is not None:
-                # the extrapolated start can be worse than the last converged
-                # state (e.g. cells it distorts): retry the step from there
-                reports.append(dict(t=t + h, h=h, failed=True, **rep))
-                trial.copy_(u)
-                rep = self.newton_solve(trial, g=g, **opts)
-            if rep["converged"]:
-                prev.copy_(u)
-                u.copy_(trial)
-                prev_h = h
-                t += h
-                reports.append(dict(t=t, h=h, **rep))
-                h = min(h_cap, 1.25 * h)
-                if checkpoint is not None:
-                    save_checkpoint(checkpoint, u=u, prev=prev, t=t, h=h, h_cap=h_cap, prev_h=prev_h,
-                                    n_steps=n_steps)
-                if on_step is not None:
-                    on_step(t, u)
-            else:
-                reports.append(dict(t=t + h, h=h, failed=True, **rep))
-                h_cap = min(h_cap, 0.9 * h)
-                h *= 0.5
-                if h < min_fraction:
-                    raise MfeError(MFE_ENOTCONV, f"load step below {min_fraction} of the path at t = {t}")
-        return reports
+            prev_h = float(ck["prev_h"])
+            st = PathState(float(ck["t"]), float(ck["h"]), float(ck["h_cap"]), 0.0 if np.isnan(prev_h) else prev_h)
+        cidx = getattr(self, "_cidx", np.zeros(0, dtype=np.int64))
+
+        def load(t):
+            dofs, vals = boundary_values(t)
+            g = np.zeros(n)
+            g[np.asarray(dofs)] = vals
+            return g[cidx]
+
+        def step(state, u_ptr, prev_ptr):
+            if checkpoint is not None:
+                save_checkpoint(checkpoint, u=u, prev=prev, t=state.t, h=state.h, h_cap=state.h_cap,
+                                prev_h=state.prev_h if state.prev_h > 0.0 else None, n_steps=n_steps)
+            if on_step is not None:
+                on_step(state.t, u)
+            return False
+
+        rc, reps = mfe_solve_load_path(self.ctx, self.solve_opts(**opts), u.data_ptr(), prev.data_ptr(), n_steps,
+                                       min_fraction, extrapolate, st, load, step, stream=_stream_handle(stream))
+        out = []
+        for r in reps:
+            d = dict(t=r.t, h=r.h)
+            if r.failed:
+                d["failed"] = True
+            d.update(r.solve.as_dict())
+            d["status"] = STATUS_NAMES.get(r.status, r.status)
+            out.append(d)
+        if rc != MFE_OK:
+            raise MfeError(rc, mfe_last_error(self.ctx))
+        return out
 
     def last_error(self):
         """Message of the last failed call on this operator ('' if none)."""

@@ -306,6 +306,7 @@ struct mfe_ctx {
     // solver work space: 8 vectors (CG r, z, p, Kp, 1/diag; Newton R, du, dg),
     // partial sums, pinned scalars, flag
     double* d_work = nullptr;
+    double* d_path = nullptr;    // load-path driver: trial state, full and compact prescribed values
     double* d_energy = nullptr;  // per-brick energy partials and their sum
     double* d_partials = nullptr;
     double* h_scalars = nullptr;
@@ -420,6 +421,7 @@ void mg_free(mfe_ctx* c) {
 void free_mesh_data(mfe_ctx* c) {
     mg_free(c);
     dfree(c->d_work);
+    dfree(c->d_path);
     dfree(c->d_energy);
     dfree(c->d_ninv);
     dfree(c->d_cinv);
@@ -584,6 +586,7 @@ void mfe_destroy(mfe_ctx* c) {
     free_mesh_data(c);
     dfree(c->d_flag);
     dfree(c->d_work);
+    dfree(c->d_path);
     dfree(c->d_net);
     dfree(c->d_partials);
     dfree(c->d_bad);
@@ -2594,6 +2597,107 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
     }
     (void)hipStreamSynchronize(s);
     if (rep) *rep = local;
+    return status;
+}
+
+int mfe_solve_load_path(mfe_ctx* c, const mfe_solve_opts* o, double* u, double* prev, int n_steps,
+                        double min_fraction, int extrapolate, mfe_path_state* state, mfe_load_fn load,
+                        void* load_user, mfe_step_fn on_step, void* step_user, mfe_path_report* reports,
+                        int max_reports, int* n_reports, void* stream) {
+    if (!c) return MFE_EINVAL;
+    c->err.clear();
+    if (n_reports) *n_reports = 0;
+    if (!c->has_mesh) return fail(c, MFE_EINVAL, "no mesh");
+    int rc = check_opts(c, o);
+    if (rc != MFE_OK) return rc;
+    if (!u) return fail(c, MFE_EINVAL, "null state vector");
+    if (extrapolate && !prev) return fail(c, MFE_EINVAL, "extrapolation needs the previous-state vector");
+    if (prev == u) return fail(c, MFE_EINVAL, "the state and previous-state vectors alias");
+    if (n_steps < 1) return fail(c, MFE_EINVAL, "n_steps must be >= 1");
+    if (!(min_fraction > 0.0 && min_fraction <= 1.0)) return fail(c, MFE_EINVAL, "min_fraction must be in (0, 1]");
+    if (c->n_con > 0 && !load) return fail(c, MFE_EINVAL, "constrained dofs need a load callback");
+    if (max_reports < 0 || (max_reports > 0 && !reports)) return fail(c, MFE_EINVAL, "bad report buffer");
+    mfe_path_state st{0.0, 0.0, 0.0, 0.0};
+    if (state) st = *state;
+    const double h0 = 1.0 / n_steps;
+    if (!(st.t >= 0.0 && st.t <= 1.0)) return fail(c, MFE_EINVAL, "path position outside [0, 1]");
+    if (!(st.h > 0.0)) st.h = h0;
+    if (!(st.h_cap > 0.0)) st.h_cap = h0;
+    if (!(st.prev_h > 0.0)) st.prev_h = 0.0;
+    DeviceGuard dg_guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n_dofs;
+    if (!c->d_path) MFE_HIP(c, hipMalloc(&c->d_path, 3 * n * sizeof(double)));
+    double* trial = c->d_path;
+    double* g = c->d_path + n;          // prescribed values at the constrained dofs, other entries unused
+    double* gc = c->d_path + 2 * n;     // the same values, compact
+    std::vector<double> vals(c->n_con);
+    int nrep = 0;
+    auto record = [&](double t, double h, bool failed, int status, const mfe_solve_report& r) {
+        if (nrep < max_reports) reports[nrep] = mfe_path_report{t, h, failed ? 1 : 0, status, r};
+        if (nrep < max_reports) ++nrep;
+        if (n_reports) *n_reports = nrep;
+    };
+    // a Newton solve ends the path only for errors other than convergence
+    auto hard = [](int r) { return r != MFE_OK && r != MFE_ENOTCONV && r != MFE_EJACOBIAN; };
+    int status = MFE_OK;
+    while (st.t < 1.0 - 1e-12) {
+        const double h = std::min(st.h, 1.0 - st.t);
+        st.h = h;
+        if (c->n_con > 0) {
+            if (load(st.t + h, vals.data(), c->n_con, load_user) != 0) {
+                status = fail(c, MFE_EINVAL, "the load callback failed");
+                break;
+            }
+            MFE_HIP(c, hipMemcpyAsync(gc, vals.data(), c->n_con * sizeof(double), hipMemcpyHostToDevice, s));
+            MFE_HIP(c, mfe::launch_scatter_indexed(c->d_cidx, c->n_con, gc, g, s));
+            // the host buffer is reused by the next step's callback
+            MFE_HIP(c, hipStreamSynchronize(s));
+        }
+        const bool extra = extrapolate && st.prev_h > 0.0;
+        if (extra) {  // trial = u + (h / prev_h) (u - prev)
+            MFE_HIP(c, mfe::launch_axpby(1.0 + h / st.prev_h, u, 0.0, trial, n, s));
+            MFE_HIP(c, mfe::launch_axpby(-h / st.prev_h, prev, 1.0, trial, n, s));
+        } else {
+            MFE_HIP(c, hipMemcpyAsync(trial, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        const double* gp = c->n_con > 0 ? g : nullptr;
+        mfe_solve_report r;
+        int nr = mfe_newton_solve(c, o, trial, gp, &r, s);
+        if (hard(nr)) { status = nr; break; }
+        if (nr != MFE_OK && extra) {
+            // the extrapolated start can be worse than the last converged
+            // state (cells it distorts): retry the step from there
+            record(st.t + h, h, true, nr, r);
+            MFE_HIP(c, hipMemcpyAsync(trial, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            nr = mfe_newton_solve(c, o, trial, gp, &r, s);
+            if (hard(nr)) { status = nr; break; }
+        }
+        if (nr == MFE_OK) {
+            if (prev) MFE_HIP(c, hipMemcpyAsync(prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            MFE_HIP(c, hipMemcpyAsync(u, trial, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            st.prev_h = h;
+            st.t += h;
+            record(st.t, h, false, nr, r);
+            st.h = std::min(st.h_cap, 1.25 * h);
+            c->err.clear();
+            if (on_step) {
+                MFE_HIP(c, hipStreamSynchronize(s));
+                if (on_step(&st, u, prev, step_user) != 0) break;
+            }
+        } else {
+            record(st.t + h, h, true, nr, r);
+            st.h_cap = std::min(st.h_cap, 0.9 * h);
+            st.h = 0.5 * h;
+            if (st.h < min_fraction) {
+                c->err.clear();
+                status = fail(c, MFE_ENOTCONV, "load step below min_fraction of the path at t = " + std::to_string(st.t));
+                break;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    if (state) *state = st;
     return status;
 }
 

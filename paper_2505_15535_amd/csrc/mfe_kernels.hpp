@@ -242,6 +242,8 @@ hipError_t launch_copy_indexed(const int64_t* idx, int64_t n, const float* src, 
 // dst[idx[i]] = a[idx[i]] - b[idx[i]]
 hipError_t launch_diff_indexed(const int64_t* idx, int64_t n, const double* a, const double* b, double* dst,
                                hipStream_t stream);
+// dst[idx[i]] = src[i] for i < n
+hipError_t launch_scatter_indexed(const int64_t* idx, int64_t n, const double* src, double* dst, hipStream_t stream);
 hipError_t launch_set_indexed(const int64_t* idx, int64_t n, double value, double* dst, hipStream_t stream);
 hipError_t launch_set_indexed(const int64_t* idx, int64_t n, float value, float* dst, hipStream_t stream);
 

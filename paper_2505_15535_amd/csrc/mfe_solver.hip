@@ -141,6 +141,13 @@ __global__ void axpy_ratio_kernel(const double* __restrict__ nd, const double* _
 }
 
 // y = a x + b y
+// dst[idx[i]] = src[i]: compact values (one per listed index) into a full vector
+__global__ void scatter_indexed_kernel(const int64_t* __restrict__ idx, int64_t n, const double* __restrict__ src,
+                                       double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = src[i];
+}
+
 __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = fma(a, x[i], b * y[i]);
@@ -265,6 +272,11 @@ hipError_t launch_axpy_ratio(const double* nd, const double* y, double* x, int64
     return hipGetLastError();
 }
 
+hipError_t launch_scatter_indexed(const int64_t* idx, int64_t n, const double* src, double* dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_indexed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx, n, src, dst);
+    return hipGetLastError();
+}
 hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kRedThreads), 0, s, a, x, b, y, n);
     return hipGetLastError();

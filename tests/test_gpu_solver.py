@@ -424,3 +424,65 @@ def test_load_path_resumes_from_checkpoint(torch_dev, tmp_path):
             op.solve_load_path(u2, bv, 3, checkpoint=ck2, resume=True, **opts)
         finally:
             op.close()
+
+
+def test_load_path_driver_through_the_c_abi(torch_dev):
+    """mfe_solve_load_path called directly: the load callback sees the
+    targets t of the steps, the step callback can stop the path (the state
+    then says where), a second call goes on from that state to t = 1 and ends
+    where an uninterrupted path ends; bad arguments are refused."""
+    import ctypes
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz, L, lam = 8, 2, 2, (4.0, 1.0, 1.0), 100.0
+    verts = synthetic.box_vertices(nx, ny, nz, L)
+    cdofs, _ = synthetic.clamp_and_twist(nx, ny, nz, 2, L, 0.0)
+    theta = np.deg2rad(16.0)
+    order = np.unique(cdofs)
+
+    def values(t):
+        d, v = synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t)
+        g = np.zeros(3 * (2 * nx + 1) * (2 * ny + 1) * (2 * nz + 1))
+        g[d] = v
+        return g[order]
+
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+    op.set_constraints(cdofs)
+    opts = op.solve_opts(strategy="t2", preconditioner="jacobi", max_newton=30, max_cg=20000, newton_atol=1e-10,
+                         cg_rtol=1e-8)
+    n = op.n_dofs
+    u = torch.zeros(n, dtype=torch.float64, device=dev)
+    prev = torch.zeros_like(u)
+    seen, steps = [], []
+    st = mfe.PathState(0.0, 0.0, 0.0, 0.0)
+    rc, reps = mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), 4, 1.0 / 64, True, st,
+                                       lambda t: seen.append(t) or values(t),
+                                       lambda s, up, pp: steps.append(s.t) or s.t >= 0.5 - 1e-12,
+                                       stream=mfe._stream_handle(None))
+    assert rc == mfe.MFE_OK and st.t == pytest.approx(0.5) and steps == pytest.approx([0.25, 0.5])
+    assert seen == pytest.approx([0.25, 0.5]) and st.prev_h == pytest.approx(0.25) and st.h == pytest.approx(0.25)
+    assert [r.failed for r in reps] == [0, 0] and all(r.solve.converged for r in reps)
+    rc, reps2 = mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), 4, 1.0 / 64, True, st, values,
+                                        stream=mfe._stream_handle(None))
+    assert rc == mfe.MFE_OK and st.t == pytest.approx(1.0) and [r.t for r in reps2] == pytest.approx([0.75, 1.0])
+    # the same path in one call
+    u1 = torch.zeros_like(u)
+    op.solve_load_path(u1, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t), 4, extrapolate=True,
+                       strategy="t2", preconditioner="jacobi", max_newton=30, max_cg=20000, newton_atol=1e-10,
+                       cg_rtol=1e-8)
+    assert torch.linalg.norm(u - u1) / torch.linalg.norm(u1) <= 1e-8
+    # bad arguments
+    for args in ((0, 1.0 / 64, False), (4, 0.0, False), (4, 2.0, False)):
+        with pytest.raises(mfe.MfeError, match="MFE_EINVAL"):
+            mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), args[0], args[1], args[2],
+                                    mfe.PathState(), values, stream=mfe._stream_handle(None))
+    # extrapolation without the previous state; no load callback with constrained dofs
+    load_cb = mfe.LOAD_FN(lambda *a: 0)
+    for prev_ptr, cb, extra in ((None, load_cb, 1), (prev.data_ptr(), mfe.LOAD_FN(), 0)):
+        rc = mfe._lib.mfe_solve_load_path(op.ctx, ctypes.byref(opts), u.data_ptr(), prev_ptr, 4, 0.1, extra, None, cb,
+                                          None, mfe.STEP_FN(), None, None, 0, None, mfe._stream_handle(None))
+        assert rc == mfe.MFE_EINVAL, op.last_error()
+    with pytest.raises(ValueError, match="constrained dofs"):   # a load callback with the wrong count
+        mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), 4, 1.0 / 64, False, mfe.PathState(),
+                                lambda t: np.zeros(3), stream=mfe._stream_handle(None))
+    op.close()
