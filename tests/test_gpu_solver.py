@@ -486,3 +486,43 @@ def test_load_path_driver_through_the_c_abi(torch_dev):
         mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), 4, 1.0 / 64, False, mfe.PathState(),
                                 lambda t: np.zeros(3), stream=mfe._stream_handle(None))
     op.close()
+
+
+def test_load_path_driver_gives_up_below_min_fraction(torch_dev):
+    """Forced from the host: with one Newton iteration allowed no step can
+    converge, so every attempt fails, the increment halves from 1/2 down to
+    min_fraction = 1/16 (attempts at 1/2, 1/4, 1/8, 1/16) and the driver
+    returns MFE_ENOTCONV with the state still at t = 0 and h_cap lowered."""
+    import paper_2505_15535_amd as mfe
+    torch, dev = torch_dev
+    nx, ny, nz, L, lam = 8, 2, 2, (4.0, 1.0, 1.0), 100.0
+    verts = synthetic.box_vertices(nx, ny, nz, L)
+    cdofs, _ = synthetic.clamp_and_twist(nx, ny, nz, 2, L, 0.0)
+    order = np.unique(cdofs)
+    theta = np.deg2rad(60.0)
+
+    def values(t):
+        d, v = synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t)
+        g = np.zeros(3 * (2 * nx + 1) * (2 * ny + 1) * (2 * nz + 1))
+        g[d] = v
+        return g[order]
+
+    op = mfe.Operator(nx, ny, nz, 2, verts, 1.0, lam, device=0)
+    op.set_constraints(cdofs)
+    opts = op.solve_opts(strategy="t2", preconditioner="jacobi", max_newton=1, max_cg=20000, newton_atol=1e-10,
+                         cg_rtol=1e-8)
+    u = torch.zeros(op.n_dofs, dtype=torch.float64, device=dev)
+    prev = torch.zeros_like(u)
+    st = mfe.PathState(0.0, 0.0, 0.0, 0.0)
+    rc, reps = mfe.mfe_solve_load_path(op.ctx, opts, u.data_ptr(), prev.data_ptr(), 2, 1.0 / 16, True, st, values,
+                                       stream=mfe._stream_handle(None))
+    assert rc == mfe.MFE_ENOTCONV and "min_fraction" in op.last_error()
+    assert [r.h for r in reps] == pytest.approx([0.5, 0.25, 0.125, 0.0625])
+    assert all(r.failed and r.status in (mfe.MFE_ENOTCONV, mfe.MFE_EJACOBIAN) for r in reps)
+    assert st.t == 0.0 and st.h_cap == pytest.approx(0.9 * 0.0625)
+    assert torch.count_nonzero(u) == 0     # the state is the last converged one
+    with pytest.raises(mfe.MfeError, match="MFE_ENOTCONV"):
+        op.solve_load_path(u, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t), 2,
+                           min_fraction=1.0 / 16, strategy="t2", preconditioner="jacobi", max_newton=1,
+                           max_cg=20000, newton_atol=1e-10, cg_rtol=1e-8)
+    op.close()
