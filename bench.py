@@ -47,10 +47,10 @@ KERNEL_SOURCES = ["paper_2505_15535_amd/csrc/mfe_kernels.hip", "paper_2505_15535
 
 
 def apply_kernel_name(strategy: str, degree: int, precision: str = "fp64") -> str:
-    """The kernel that runs an apply on a structured box: the wavefront-per-two-
-    cells kernel for Q2 (FP64: cached and dual-number strategies; FP32: all),
-    else the brick kernel."""
-    wave = degree == 2 and (precision == "fp32" or strategy in ("t2", "t4", "otf_ad"))
+    """The kernel that runs an apply on a structured box (default summation
+    order): the wavefront-per-two-cells kernel for the cached strategies at Q2
+    and for the geometry-cached one with FP32 vectors, else the brick kernel."""
+    wave = degree == 2 and (strategy in ("t2", "t4") or (strategy == "otf_geom" and precision == "fp32"))
     return ("wave_kernel" if wave else "cell_kernel") + f" apply {strategy} {precision}"
 
 
@@ -633,7 +633,7 @@ def main(argv=None):
         op.close()
         line = {"metric": METRIC, "legs": sorted(legs)}
         if "mixed" in legs:
-            line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup)
+            line["mixed"] = {m: mixed_leg(m, args.steps, args.warmup, precisions=mixed_precs)
                              for m in [cfg.name] + [m for m in args.mixed.split(",") if m and m != cfg.name]}
         if "split" in legs:
             line["split"] = split_leg(cfg.name, args.steps, args.warmup)

@@ -83,3 +83,14 @@ def test_measured_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("box48_q2", "t2") == 123
     assert bench.measured_traffic("box48_q2", "t4") is None
     assert bench.measured_traffic("box48_q2", "otf") is None
+
+
+@pytest.mark.parametrize("strategy,degree,precision,kernel", [
+    ("t2", 2, "fp64", "wave_kernel"), ("t4", 2, "fp32", "wave_kernel"), ("otf", 2, "fp64", "cell_kernel"),
+    ("otf", 2, "fp32", "cell_kernel"), ("otf_ad", 2, "fp64", "cell_kernel"), ("otf_geom", 2, "fp64", "cell_kernel"),
+    ("otf_geom", 2, "fp32", "wave_kernel"), ("t2", 4, "fp64", "cell_kernel"), ("t4", 6, "fp32", "cell_kernel")])
+def test_kernel_label_follows_the_routing(strategy, degree, precision, kernel):
+    """The roofline's kernel label names the kernel the library routes the
+    apply to (the cached strategies and the FP32 geometry-cached one on Q2
+    boxes run in the wavefront kernel, the rest in the brick kernel)."""
+    assert bench.apply_kernel_name(strategy, degree, precision) == f"{kernel} apply {strategy} {precision}"
