@@ -9,7 +9,7 @@ build time is reported separately).  Every strategy is timed; the headline
 `value` is the fastest one; kernel durations (roofline) come from every
 10th launch of the timed steps.  Beside it, under "mixed": FP64 applies and
 applies with FP32 vectors and caches whose sweeps run in FP32 on the vector
-ALUs or on the matrix cores (bf16x3, bf16), on the Q4 24^3 and Q6 12^3 boxes
+ALUs (with --mfma also on the matrix cores: bf16x3, bf16), on the Q4 24^3 and Q6 12^3 boxes
 (and the headline box), with the error of each against the FP64 result; per
 strategy, "cold" times the apply with the caches flushed between applies;
 "cpu_csr" is the assembled-matrix product on the host cores; under "hex": the apply on
@@ -22,7 +22,8 @@ seconds (default 0.3), so that the timed steps run at its steady clocks.
 Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box48_q2]
-                  [--mixed box24_q4,box12_q6] [--no-newton] [--settle 0.3]
+                  [--mixed box24_q4,box12_q6] [--mfma] [--no-newton] [--settle 0.3]
+                  [--legs apply,mixed,split,hex,newton,learned] [--out FILE]
 """
 
 from __future__ import annotations
