@@ -149,9 +149,10 @@ def measured_traffic(workload: str, strategy: str):
 
 
 # --------------------------------------------------------------------------- CPU baseline
-def cpu_baseline(cfg, target_s: float = 12.0) -> dict:
+def cpu_baseline(cfg, target_s: float = 12.0, product=None) -> dict:
     """The FP64 oracle's naive cell loop (as it stands) on a bounded sample of
-    the workload's cells, scaled to DoF/s of a whole apply."""
+    the workload's cells, scaled to DoF/s of a whole apply.  When the sample
+    is every cell, product["naive_loop"] receives the oracle's v = K(u) w."""
     import numpy as np
     from oracle.fem import Problem
     from oracle.mesh import BoxMesh
@@ -164,17 +165,31 @@ def cpu_baseline(cfg, target_s: float = 12.0) -> dict:
     while True:
         cells = np.arange(min(n_cells, mesh.n_elems))
         c0, t0 = time.process_time(), time.perf_counter()
-        P.apply_naive(u, w, elems=cells)
+        v_or = P.apply_naive(u, w, elems=cells)
         t_wall, t_cpu = time.perf_counter() - t0, time.process_time() - c0
         if t_wall >= target_s or n_cells >= mesh.n_elems:
             break
         n_cells = min(mesh.n_elems, int(n_cells * max(2.0, min(8.0, 1.2 * target_s / max(t_wall, 1e-3)))))
     frac = len(cells) / mesh.n_elems
     rate = cfg.n_dofs * frac / t_wall / 1e9
+    if product is not None and len(cells) == mesh.n_elems:
+        product["naive_loop"] = v_or
     return {"value": rate, "unit": "GDoF/s", "cores": max(1, int(round(t_cpu / t_wall))), "kind": "oracle",
             "sample": f"naive FP64 cell loop (explicit 81-entry tangent, numpy) over {len(cells)} of "
                       f"{mesh.n_elems} cells of {cfg.name} in {t_wall:.1f} s, scaled by the cell fraction",
             "host_threads": os.cpu_count(), "host": host_cpu()}
+
+
+def oracle_check(v_gpu: dict, products: dict) -> dict:
+    """Relative 2-norm error of every strategy's timed GPU result against the
+    oracle's full-size products (the naive cell loop and the assembled CSR
+    product, each when it ran over the whole workload), every dof compared."""
+    import numpy as np
+    out = {}
+    for kind, ref in products.items():
+        nr = float(np.linalg.norm(ref))
+        out[kind] = {s: float(np.linalg.norm(v - ref) / nr) for s, v in v_gpu.items()}
+    return out
 
 
 def host_cpu() -> dict:
@@ -192,7 +207,7 @@ def host_cpu() -> dict:
     return {"model": model, "logical_cpus": n}
 
 
-def cpu_csr_baseline(cfg) -> dict:
+def cpu_csr_baseline(cfg, product=None) -> dict:
     """The assembled-matrix alternative the paper compares against (Sec.
     3.2.2) at the headline workload's full size: the oracle's tangent of the
     same box, state and material assembled into CSR by the oracle's C/OpenMP
@@ -225,6 +240,8 @@ def cpu_csr_baseline(cfg) -> dict:
                                y.ctypes.data)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times[1:]))
+    if product is not None:
+        product["assembled_csr"] = y
     nnz = int(indptr[-1])
     mb = (data.nbytes + indices.nbytes + indptr.nbytes) / 1e6
     del indptr, indices, data
@@ -582,6 +599,7 @@ def main(argv=None):
     state_ms = (time.perf_counter() - t0) * 1e3
 
     results = {}
+    v_host = {}   # each strategy's v = K(u) w, for the whole-vector check against the oracle
     if strategies:
         flush_src = torch.ones(1 << 26, dtype=torch.float64, device=dev)   # 512 MiB each
         flush_dst = torch.empty_like(flush_src)
@@ -605,6 +623,7 @@ def main(argv=None):
         op.set_timing(False)
         if not np.isfinite(float(v.abs().max())):
             raise RuntimeError(f"non-finite result for strategy {s}")
+        v_host[s] = v.cpu().numpy()
         # cold: a 1 GiB copy between applies evicts the L2s and the 256 MB
         # Infinity Cache, so the vectors come from HBM as well (kernel time only)
         op.set_timing(True)
@@ -687,12 +706,17 @@ def main(argv=None):
         line["learned"] = learned_leg()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cfg)
+        products = {}
+        line["cpu_baseline"] = cpu_baseline(cfg, product=products)
         print("[bench] timing the assembled-CSR product on the host cores", file=sys.stderr, flush=True)
         try:
-            line["cpu_csr"] = cpu_csr_baseline(cfg)
+            line["cpu_csr"] = cpu_csr_baseline(cfg, product=products)
         except (OSError, RuntimeError) as e:   # a host without the built oracle library or OpenMP
             line["cpu_csr"] = {"value": None, "error": str(e)}
+        if v_host and products:
+            line["oracle_check"] = oracle_check(v_host, products)
+            print(f"[bench] whole-vector error against the oracle: {line['oracle_check']}", file=sys.stderr,
+                  flush=True)
     text = json.dumps(line)
     print(text, flush=True)
     if args.out:

@@ -94,3 +94,12 @@ def test_kernel_label_follows_the_routing(strategy, degree, precision, kernel):
     apply to (the cached strategies and the FP32 geometry-cached one on Q2
     boxes run in the wavefront kernel, the rest in the brick kernel)."""
     assert bench.apply_kernel_name(strategy, degree, precision) == f"{kernel} apply {strategy} {precision}"
+
+
+def test_oracle_check_is_the_relative_error_of_every_strategy():
+    import numpy as np
+    ref = np.array([3.0, 4.0])
+    out = bench.oracle_check({"t2": ref + np.array([0.0, 5e-3]), "otf": ref.copy()},
+                             {"assembled_csr": ref, "naive_loop": 2 * ref})
+    assert out["assembled_csr"]["t2"] == pytest.approx(1e-3) and out["assembled_csr"]["otf"] == 0.0
+    assert out["naive_loop"]["otf"] == pytest.approx(0.5)
