@@ -110,6 +110,24 @@ def test_training_resumes_from_checkpoint(torch_dev, tmp_path):
     assert resumed == losses[2:]
     assert torch.equal(a.w, b.w) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v) and a.step == b.step
 
+
+def test_training_loop_resumes_from_its_checkpoint(torch_dev, tmp_path):
+    """learned.train stopped after one epoch and resumed from its checkpoint
+    (network, Adam moments, epoch, shuffling generator, loss history) goes on
+    as the uninterrupted run does: the same epoch losses and parameters, to
+    the rounding of the applies' atomic sums."""
+    from paper_2505_15535_amd import learned
+    torch, dev = torch_dev
+    data = learned.generate([(60.0, 100.0)], nx=16, ny=8, nz=8, steps=2, states_per_path=1, n_loads=1, seed=2,
+                            cg_stages=(0, 2))
+    full, hist = learned.train(data, nx=16, ny=8, nz=8, epochs=3, lr=1e-3, seed=4)
+    ck = tmp_path / "train.npz"
+    _, h1 = learned.train(data, nx=16, ny=8, nz=8, epochs=1, lr=1e-3, seed=4, checkpoint=ck)
+    back, h3 = learned.train(data, nx=16, ny=8, nz=8, epochs=3, lr=1e-3, seed=4, checkpoint=ck, resume=True)
+    assert len(h1) == 1 and len(h3) == 3 and h3[0] == h1[0] and back.step == full.step
+    assert h3 == pytest.approx(hist, rel=1e-6)
+    assert _rel(back.params(), full.params()) <= 1e-5
+
 def test_patch_gather_scatter_and_invariants(torch_dev):
     import paper_2505_15535_amd as mfe
     torch, dev = torch_dev
