@@ -338,6 +338,17 @@ typedef struct mfe_solve_opts {
                              `forcing` (also eta_0), at least cg_rtol and at least
                              0.5 newton_atol / ||R_k||; the first correction of a
                              load step (the boundary increment) uses cg_rtol */
+    int mg_lag;           /* GMG inside mfe_newton_solve: 0 = every CG solve
+                             re-estimates the smoothed levels' spectra and
+                             refactors the coarsest level; k > 0 = after such a
+                             full set-up the next k CG solves of the same Newton
+                             solve keep those estimates and that inverse (a
+                             lagged preconditioner: the level states, caches,
+                             diagonals and operators are always the current
+                             ones); a CG solve that stops early and the
+                             boundary increment's solve make the next set-up a
+                             full one.  mfe_cg_solve and mfe_gmg_setup always
+                             set up in full */
 } mfe_solve_opts;
 
 #define MFE_HISTORY 64

@@ -54,7 +54,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("strategy", _i), ("preconditioner", _i), ("max_newton", _i), ("max_cg", _i),
                 ("newton_atol", _d), ("cg_rtol", _d), ("mg_levels", _i), ("cheb_degree", _i),
                 ("cheb_range", _d), ("coarse_degree", _i), ("coarse_range", _d), ("mg_precision", _i),
-                ("mg_graph", _i), ("coarse_direct", _i), ("forcing", _d)]
+                ("mg_graph", _i), ("coarse_direct", _i), ("forcing", _d), ("mg_lag", _i)]
 
 
 class SolveReport(ctypes.Structure):
@@ -584,12 +584,12 @@ class Operator:
     @staticmethod
     def solve_opts(strategy="t2", preconditioner="jacobi", max_newton=20, max_cg=5000, newton_atol=1e-8,
                    cg_rtol=1e-6, mg_levels=0, cheb_degree=4, cheb_range=15.0, coarse_degree=15,
-                   coarse_range=200.0, mg_precision="fp64", mg_graph=1, coarse_direct=1, forcing=0.0):
+                   coarse_range=200.0, mg_precision="fp64", mg_graph=1, coarse_direct=1, forcing=0.0, mg_lag=0):
         return SolveOpts(STRATEGIES.get(strategy, strategy), PRECONDITIONERS.get(preconditioner, preconditioner),
                          int(max_newton), int(max_cg), float(newton_atol), float(cg_rtol), int(mg_levels),
                          int(cheb_degree), float(cheb_range), int(coarse_degree), float(coarse_range),
                          PRECISIONS.get(mg_precision, mg_precision), int(mg_graph), int(coarse_direct),
-                         float(forcing))
+                         float(forcing), int(mg_lag))
 
     def newton_solve(self, u, g=None, stream=None, **opts):
         """Solve R(u) = 0 in place; g (optional tensor) holds new Dirichlet values at the

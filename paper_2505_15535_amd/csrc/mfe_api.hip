@@ -334,6 +334,10 @@ struct mfe_ctx {
     int* d_bad_dense = nullptr;
     hipGraphExec_t mg_exec = nullptr;
     bool mg_graph_valid = false;
+    // lagged multigrid set-up: CG solves left that may reuse the spectrum
+    // estimates and the coarse inverse, and the options they were made with
+    int mg_lag_left = 0;
+    int mg_lag_prec = -1, mg_lag_direct = -1;
     const double* mg_graph_r = nullptr;
     double* mg_graph_z = nullptr;
     int mg_graph_prec = -1;
@@ -416,6 +420,7 @@ void mg_free(mfe_ctx* c) {
     if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
     c->mg_exec = nullptr;
     c->mg_graph_valid = false;
+    c->mg_lag_left = 0;
 }
 
 void free_mesh_data(mfe_ctx* c) {
@@ -1191,6 +1196,7 @@ int check_opts(mfe_ctx* c, const mfe_solve_opts* o) {
             return fail(c, MFE_EINVAL, "mg_precision must be MFE_FP64 or MFE_SF_FP32");
         if (o->mg_graph != 0 && o->mg_graph != 1) return fail(c, MFE_EINVAL, "mg_graph must be 0 or 1");
         if (o->coarse_direct != 0 && o->coarse_direct != 1) return fail(c, MFE_EINVAL, "coarse_direct must be 0 or 1");
+        if (o->mg_lag < 0) return fail(c, MFE_EINVAL, "mg_lag must be >= 0");
     }
     if (o->max_cg < 1 || o->max_newton < 1) return fail(c, MFE_EINVAL, "iteration limits must be >= 1");
     if (!(o->cg_rtol > 0.0) || !(o->newton_atol >= 0.0)) return fail(c, MFE_EINVAL, "bad tolerances");
@@ -1684,6 +1690,59 @@ int dense_finish(mfe_ctx* c, MGLevel& L, bool fp32, hipStream_t s, bool& ok) {
 const double* dense_of(const MGLevel& L, double*) { return L.dense; }
 const float* dense_of(const MGLevel& L, float*) { return L.dense32; }
 
+// The coarsest level's direct-solve set-up (one workgroup, ~0.6 ms) runs on
+// the side stream while the other levels' eigenvalue estimates run on s; a
+// failed pivot check falls back to smoothing that level.
+int mg_spectra(mfe_ctx* c, const mfe_solve_opts* o, bool fp32, hipStream_t s) {
+    const size_t nl = c->mg.size();
+    MGLevel& Lc = c->mg[nl - 1];
+    for (MGLevel& L : c->mg) L.dense_ok = false;
+    bool dense = false;
+    // an early return leaves no side-stream work behind
+    struct SideGuard {
+        hipStream_t side = nullptr;
+        ~SideGuard() {
+            if (side) (void)hipStreamSynchronize(side);
+        }
+    } guard;
+    {
+        const int64_t n_free = Lc.ctx->n_dofs - Lc.ctx->n_con;
+        if (o->coarse_direct && Lc.ctx->n_dofs <= 1024 && n_free > 0 && n_free <= mfe::kDenseMax) {
+            if (!c->side_stream) MFE_HIP(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+            if (!c->side_fork) MFE_HIP(c, hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming));
+            if (!c->side_join) MFE_HIP(c, hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming));
+            MFE_HIP(c, hipEventRecord(c->side_fork, s));
+            MFE_HIP(c, hipStreamWaitEvent(c->side_stream, c->side_fork, 0));
+            guard.side = c->side_stream;
+            const int rc = dense_launch(c, Lc, c->side_stream, dense);
+            if (rc != MFE_OK) return rc;
+            MFE_HIP(c, hipEventRecord(c->side_join, c->side_stream));
+        }
+    }
+    {
+        // spectrum estimates of the smoothed levels, all at once (the
+        // coarsest one too unless its direct solve is being set up)
+        std::vector<MGLevel*> est;
+        for (size_t l = 0; l + 1 < nl; ++l) est.push_back(&c->mg[l]);
+        if (!dense) est.push_back(&Lc);
+        int rc = lanczos_levels(c, est, s);
+        if (rc != MFE_OK) return rc;
+        if (dense) {
+            MFE_HIP(c, hipStreamWaitEvent(s, c->side_join, 0));
+            rc = dense_finish(c, Lc, fp32, s, Lc.dense_ok);
+            if (rc != MFE_OK) return rc;
+            guard.side = nullptr;  // joined: dense_finish waited for it
+            if (Lc.dense_ok) {
+                Lc.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
+            } else {
+                rc = lanczos_levels(c, std::vector<MGLevel*>{&Lc}, s);
+                if (rc != MFE_OK) return rc;
+            }
+        }
+    }
+    return MFE_OK;
+}
+
 int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
     const bool cached = o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD;
     const bool fp32 = o->mg_precision == MFE_SF_FP32;
@@ -1737,54 +1796,21 @@ int mg_update(mfe_ctx* c, const mfe_solve_opts* o, hipStream_t s) {
             }
         if (flags[nlv]) return fail(c, MFE_EJACOBIAN, "level tangent diagonal is not positive: no Chebyshev-Jacobi smoother");
     }
-    // The coarsest level's direct-solve set-up (one workgroup, ~0.6 ms) runs
-    // on the side stream while the other levels' eigenvalue estimates run on
-    // s; a failed pivot check falls back to smoothing that level.
+    // A lagged set-up keeps the spectrum estimates and the coarse inverse of
+    // the last full one (same V-cycle precision and coarse mode); the level
+    // operators, caches and diagonals above are always the current ones.
     const size_t nl = c->mg.size();
-    MGLevel& Lc = c->mg[nl - 1];
-    for (MGLevel& L : c->mg) L.dense_ok = false;
-    bool dense = false;
-    // an early return leaves no side-stream work behind
-    struct SideGuard {
-        hipStream_t side = nullptr;
-        ~SideGuard() {
-            if (side) (void)hipStreamSynchronize(side);
-        }
-    } guard;
-    {
-        const int64_t n_free = Lc.ctx->n_dofs - Lc.ctx->n_con;
-        if (o->coarse_direct && Lc.ctx->n_dofs <= 1024 && n_free > 0 && n_free <= mfe::kDenseMax) {
-            if (!c->side_stream) MFE_HIP(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-            if (!c->side_fork) MFE_HIP(c, hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming));
-            if (!c->side_join) MFE_HIP(c, hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming));
-            MFE_HIP(c, hipEventRecord(c->side_fork, s));
-            MFE_HIP(c, hipStreamWaitEvent(c->side_stream, c->side_fork, 0));
-            guard.side = c->side_stream;
-            const int rc = dense_launch(c, Lc, c->side_stream, dense);
-            if (rc != MFE_OK) return rc;
-            MFE_HIP(c, hipEventRecord(c->side_join, c->side_stream));
-        }
-    }
-    {
-        // spectrum estimates of the smoothed levels, all at once (the
-        // coarsest one too unless its direct solve is being set up)
-        std::vector<MGLevel*> est;
-        for (size_t l = 0; l + 1 < nl; ++l) est.push_back(&c->mg[l]);
-        if (!dense) est.push_back(&Lc);
-        int rc = lanczos_levels(c, est, s);
+    const bool lag = o->mg_lag > 0 && c->mg_lag_left > 0 && c->mg_lag_prec == o->mg_precision &&
+                     c->mg_lag_direct == o->coarse_direct;
+    if (lag) {
+        --c->mg_lag_left;
+    } else {
+        c->mg_lag_left = 0;
+        const int rc = mg_spectra(c, o, fp32, s);
         if (rc != MFE_OK) return rc;
-        if (dense) {
-            MFE_HIP(c, hipStreamWaitEvent(s, c->side_join, 0));
-            rc = dense_finish(c, Lc, fp32, s, Lc.dense_ok);
-            if (rc != MFE_OK) return rc;
-            guard.side = nullptr;  // joined: dense_finish waited for it
-            if (Lc.dense_ok) {
-                Lc.lmax = 0.0;  // solved, not smoothed: no spectrum estimate needed
-            } else {
-                rc = lanczos_levels(c, std::vector<MGLevel*>{&Lc}, s);
-                if (rc != MFE_OK) return rc;
-            }
-        }
+        c->mg_lag_left = o->mg_lag;
+        c->mg_lag_prec = o->mg_precision;
+        c->mg_lag_direct = o->coarse_direct;
     }
     for (size_t l = 0; l < nl; ++l) {
         MGLevel& L = c->mg[l];
@@ -2385,6 +2411,7 @@ int mfe_gmg_setup(mfe_ctx* c, const mfe_solve_opts* o, void* stream) {
     }
     rc = mg_build(c, o2.mg_levels);
     if (rc != MFE_OK) return rc;
+    c->mg_lag_left = 0;  // a set-up on request is a full one
     return mg_update(c, &o2, s);
 }
 
@@ -2435,6 +2462,7 @@ int mfe_cg_solve(mfe_ctx* c, const mfe_solve_opts* o, const double* b, double* x
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = ensure_work(c);
     if (rc != MFE_OK) return rc;
+    c->mg_lag_left = 0;  // a CG solve on its own sets the multigrid up in full
     if (o->strategy != MFE_OTF && o->strategy != MFE_OTF_AD) {
         const int slot = cache_slot(o->strategy);
         if (!c->cache_valid[slot] || (slot > 0 && c->cache_version[slot] != c->state_version)) {
@@ -2465,6 +2493,7 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = ensure_work(c);
     if (rc != MFE_OK) return rc;
+    c->mg_lag_left = 0;  // the first CG solve sets the multigrid up in full
     const int64_t n = c->n_dofs;
     double* res = c->d_work + 5 * n;   // residual, then the right-hand side
     double* du = c->d_work + 6 * n;    // Newton correction
@@ -2532,6 +2561,9 @@ int mfe_newton_solve(mfe_ctx* c, const mfe_solve_opts* o, double* u, const doubl
         double rel = 0.0;
         rc = cg(c, &oc, res, du, s, iters, rel, &local.pc_fallbacks, &local.net_fallbacks);
         local.cg_iterations += iters;
+        // no lagged set-up after a solve that stopped early, nor after the
+        // boundary increment, which moves the state furthest
+        if (rc != MFE_OK || boundary_step) c->mg_lag_left = 0;
         if (rc != MFE_OK && rc != MFE_ENOTCONV) { status = rc; break; }
         c->err.clear();
         local.newton_iterations = it + 1;

@@ -218,7 +218,7 @@ def test_gmg_per_cell_material_and_options(torch_dev):
     assert status == "MFE_OK" and it < 60
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-8
     for bad in ({"cheb_degree": 0}, {"cheb_range": 1.0}, {"coarse_degree": 0}, {"coarse_range": float("nan")},
-                {"mg_levels": -1}, {"mg_precision": 2}, {"mg_graph": 2}):
+                {"mg_levels": -1}, {"mg_precision": 2}, {"mg_graph": 2}, {"mg_lag": -1}):
         with pytest.raises(mfe.MfeError, match="MFE_EINVAL"):
             op.cg_solve(_to(torch_dev, b), preconditioner="gmg", **bad)
 
@@ -255,10 +255,12 @@ def test_newton_twisted_beam_parity(torch_dev):
     assert np.linalg.norm(P.residual(ug)) <= 1e-9
 
 
-@pytest.mark.parametrize("strategy,mg_precision", [("t4", "fp64"), ("t2", "fp32")])
-def test_newton_twisted_beam_gmg(torch_dev, strategy, mg_precision):
+@pytest.mark.parametrize("strategy,mg_precision,mg_lag", [("t4", "fp64", 0), ("t2", "fp32", 0), ("t2", "fp64", 3),
+                                                           ("t2", "fp32", 2)])
+def test_newton_twisted_beam_gmg(torch_dev, strategy, mg_precision, mg_lag):
     """The same load path with the GMG preconditioner (8x2x2 -> 4x1x1), FP64
-    or FP32 V-cycle: converges to the oracle's solution."""
+    or FP32 V-cycle, with a full multigrid set-up for every CG solve or a
+    lagged one: converges to the oracle's solution."""
     import paper_2505_15535_amd as mfe
     torch, dev = torch_dev
     nx, ny, nz, L, lam = 8, 2, 2, (4.0, 1.0, 1.0), 100.0
@@ -276,7 +278,7 @@ def test_newton_twisted_beam_gmg(torch_dev, strategy, mg_precision):
     u = torch.zeros(mesh.n_dofs, dtype=torch.float64, device=dev)
     reps = op.solve_load_path(u, lambda t: synthetic.clamp_and_twist(nx, ny, nz, 2, L, theta * t), 3,
                               strategy=strategy, preconditioner="gmg", mg_precision=mg_precision,
-                              max_newton=30, max_cg=5000, newton_atol=1e-10, cg_rtol=1e-8)
+                              mg_lag=mg_lag, max_newton=30, max_cg=5000, newton_atol=1e-10, cg_rtol=1e-8)
     print(reps)
     assert all(r["converged"] for r in reps if not r.get("failed"))
     ug = u.cpu().numpy()
