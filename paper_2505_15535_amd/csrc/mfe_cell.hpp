@@ -802,13 +802,14 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
     };
 
     if constexpr (MI::vertex_geom) {
-        // the 12 edge vectors of every cell's trilinear map
-        for (int t = tid; t < G::CPB * 36; t += G::NT) {
-            const int c = t / 36;
-            const int r = t - 36 * c;
+        // the 12 edge vectors of every cell's trilinear map, one thread per
+        // (cell, edge) for its three components (fewer wavefronts spend
+        // index arithmetic here than with one thread per component)
+        for (int t = tid; t < G::CPB * 12; t += G::NT) {
+            const int c = t / 12;
+            const int edge = t - 12 * c;
             const int cx = c % G::BX, cy = (c / G::BX) % G::BY, cz = c / (G::BX * G::BY);
             if (cx >= bp.ncx || cy >= bp.ncy || cz >= bp.ncz) continue;
-            const int edge = r / 3, d = r - 3 * edge;
             const int dir = edge >> 2, a = edge & 3;
             int v0;  // edge = 4*dir + a; its end points differ in bit `dir`
             if (dir == 0) v0 = ((a & 1) << 1) | ((a >> 1) << 2);
@@ -825,7 +826,8 @@ void cell_kernel(const KParams p, const Tables<N> T, const Tables<N, R> TR, cons
                 vid0 = (ex + (v0 & 1)) + (p.nx + 1) * ((ey + ((v0 >> 1) & 1)) + (p.ny + 1) * (ez + (v0 >> 2)));
                 vid1 = (ex + (v1 & 1)) + (p.nx + 1) * ((ey + ((v1 >> 1) & 1)) + (p.ny + 1) * (ez + (v1 >> 2)));
             }
-            sEdge[t] = p.verts[3 * vid1 + d] - p.verts[3 * vid0 + d];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sEdge[36 * c + 3 * edge + d] = p.verts[3 * vid1 + d] - p.verts[3 * vid0 + d];
         }
     }
 
